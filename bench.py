@@ -1,0 +1,173 @@
+"""Benchmark of the RHS + RK3 hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload: the channel-like block 512x256x256 in FP64 (periodic x/z,
+isothermal tanh-stretched walls in y, bulk Mach 1.5, Re_b 6000, sixth-order
+central split-form convection + sixth-order Laplacian viscous terms), seeded
+synthetic input, inputs resident in HBM before the timed region. One step =
+one full RK3 step (three fused RHS/update substeps + ghost fills).
+
+Prints one JSON line: throughput (grid-point updates per second per RK3
+step), the roofline of the dominant kernel (the fused RHS/update kernel,
+timed live with HIP events on its stream) and the CPU oracle baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+# Algorithmic HBM bytes per interior point of one RK3 step: 3 reads + 3
+# writes of the 5 FP64 conserved variables, the RK register written in
+# substeps 1-2 and read in substeps 2-3 -> (6 + 4) * 40 B.
+ALG_BYTES_PER_POINT_STEP = 400.0
+SUBSTEPS = 3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle timing (profiling runs)")
+    ap.add_argument("--cpu-sample-steps", type=int, default=1)
+    return ap.parse_args()
+
+
+def load_traffic(kernel: str):
+    """Counter-measured HBM bytes per launch from profiles/, if recorded for
+    the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+        import hashlib
+        src = os.path.join(ROOT, "paper_2304_05494_amd", "csrc", "sx_rhs.hip")
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if rec.get("kernel") != kernel or rec.get("source_sha256") != digest:
+            return None
+        return float(rec["bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def cpu_baseline(case, Wn, dt, steps):
+    """The oracle, as is, timed on this host on RK3 steps of the same grid."""
+    import numpy as np
+    import oracle as O
+    p = O.Params(**{k: getattr(case, k) for k in O.Params.__dataclass_fields__})
+    o = O.Oracle(p)
+    W = Wn.copy()
+    Rp = np.zeros((5, case.nz, case.ny, case.nx))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        o.rk3_step(W, Rp, dt)
+    el = time.perf_counter() - t0
+    return {"value": case.points * steps / el, "unit": "grid-point updates/s per RK3 step",
+            "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"{steps} RK3 step(s) of the full {case.nx}x{case.ny}x{case.nz} workload "
+                      f"({el:.1f} s, OpenMP over z-planes)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2304_05494_amd import inputs, sx
+
+    case = inputs.channel_case()
+    Wn = np.ascontiguousarray(inputs.fields(case))
+    h = sx.Handle(case)
+    W0 = h.to_layout(Wn)
+    h.sx_bind(W0)
+    dt = h.sx_compute_dt(case.cfl)
+    for _ in range(args.warmup):
+        h.sx_rk3_step(dt)
+    torch.cuda.synchronize()
+
+    h.sx_timing_enable(True)
+    h.sx_timing_read()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    for _ in range(args.steps):
+        h.sx_rk3_step(dt)
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = start.elapsed_time(stop)
+    launches, kern_ms = h.sx_timing_read()
+    h.sx_timing_enable(False)
+
+    d = h.sx_diagnostics()
+    ok = d.status == sx.SX_OK
+    ms_per_step = ms_total / args.steps
+    value = case.points / (ms_per_step * 1e-3)
+    avg_launch_s = kern_ms / launches * 1e-3
+    alg_bytes_launch = ALG_BYTES_PER_POINT_STEP / SUBSTEPS * case.points
+    achieved = alg_bytes_launch / avg_launch_s / 1e9
+    kernel = "k_rhs_central<3,64,4,true>"
+    traffic = load_traffic(kernel)
+    line = {
+        "metric": "grid-point updates/s per RK3 step (FP64 vs FP32-flux) + % HBM roofline",
+        "value": value,
+        "unit": "grid-point updates/s per RK3 step",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "channel-like block 512x256x256 FP64: periodic x/z, isothermal no-slip "
+                        "walls in y (tanh stretching beta=1.8), bulk Mach 1.5, Re_b 6000, "
+                        "laminar profile + 5% seeded Gaussian velocity noise (seed 2), "
+                        "C6 central split-form convection + V6 Laplacian viscous terms, "
+                        "RK3 (Wray) at CFL 0.5",
+            "nx": case.nx, "ny": case.ny, "nz": case.nz, "points": case.points,
+            "dt": dt, "precision": "fp64",
+        },
+        "alg_fraction": value * ALG_BYTES_PER_POINT_STEP / (HBM_PEAK_GBS * 1e9),
+        "roofline": {
+            "bound": "hbm",
+            "kernel": kernel,
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None if traffic is None else traffic,
+            "launch_ms": avg_launch_s * 1e3,
+            "launches": launches,
+            "alg_bytes_per_launch": alg_bytes_launch,
+        },
+        "state_ok": ok,
+        "wall_s_timed": wall,
+    }
+    if not args.no_cpu_baseline:
+        del h, W0
+        torch.cuda.empty_cache()
+        line["cpu_baseline"] = cpu_baseline(case, Wn, dt, args.cpu_sample_steps)
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,195 @@
+/*
+ * sx.h -- C ABI of the MI355X (gfx950) right-hand-side / RK3 library for the
+ * compressible Navier-Stokes hot path of STREAmS-2 (Sathyanarayana et al.,
+ * "High-speed turbulent flows towards the exascale: STREAmS-2 porting and
+ * performance").
+ *
+ * What is computed (Section 2 of the paper): on a Cartesian grid stretched
+ * in y, the right-hand side R = dW/dt of W = (rho, rho u, rho v, rho w, rho E)
+ * made of the convective derivatives in x, y, z (skew-symmetric split form
+ * cast as face fluxes, hybridised with WENO characteristic fluxes where a
+ * modified Ducros sensor flags a face), the Laplacian-form viscous and
+ * heat-flux terms, and the third-order low-storage Runge-Kutta update. The
+ * kernel names of the paper's Table 2 map onto this library as:
+ * euler_{x,y,z}_{central,weno} + visflx + update_flux -> sx_rhs / sx_rk3_step,
+ * compute_dt -> sx_compute_dt, compute_residual -> sx_diagnostics.
+ *
+ * Conventions
+ *  - All device pointers are HIP device pointers owned by the caller unless
+ *    stated otherwise; the library never frees them.
+ *  - Every function returns an sx_status; none aborts or throws. On failure
+ *    sx_last_error() describes the cause.
+ *  - Calls are asynchronous on the stream given to sx_bind() unless stated.
+ *    One handle per stream; a handle is not thread-safe.
+ *  - Ghosted state layout (the C form of the Fortran w(x,y,z,v) array of the
+ *    paper's Section 3.2): double W[5][pz][py][px], x fastest. Interior node
+ *    (i,j,k), 0 <= i < nx etc., of variable v sits at
+ *        v*var_stride + (k+ng)*px*py + (j+ng)*px + (i+ox)
+ *    with ng ghost layers in every direction; columns [ox-ng, ox) and
+ *    [ox+nx, ox+nx+ng) are x ghosts, the rest of a row is padding that is
+ *    never read. ox is chosen so interior rows start 128-byte aligned.
+ *  - Interior arrays (R, Rprev) are dense double R[5][nz][ny][nx] (the
+ *    paper's fln array, no ghosts).
+ */
+#ifndef SX_H
+#define SX_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SX_OK = 0,
+    SX_EINVAL = 1,        /* bad argument: order, size, null pointer, layout */
+    SX_EUNSUPPORTED = 2,  /* valid request this build does not implement */
+    SX_EHIP = 3,          /* HIP runtime error (detail in sx_last_error) */
+    SX_ENOMEM = 4,        /* device allocation failed */
+    SX_ENONFINITE = 5,    /* diagnostics found non-finite or non-physical state */
+    SX_ESTATE = 6         /* call order violated (e.g. step before bind) */
+} sx_status;
+
+/* Boundary condition of one face. */
+enum {
+    SX_BC_PERIODIC = 0,   /* both faces of a direction must be periodic */
+    SX_BC_WALL = 1,       /* isothermal no-slip wall by reflection (T_wall) */
+    SX_BC_EXTRAP = 2,     /* zeroth-order extrapolation (outflow) */
+    SX_BC_FROZEN = 3      /* Dirichlet: ghost cells keep the caller's values */
+};
+
+/* y mapping of the uniform index coordinate eta. */
+enum {
+    SX_Y_UNIFORM = 0,     /* y_j = y0 + j ly/ny */
+    SX_Y_TANH2 = 1,       /* two walls at the faces y = -ly/2, +ly/2 */
+    SX_Y_TANH1 = 2        /* one wall at the face y = 0, top face y = ly */
+};
+
+/* term_mask bits of sx_rhs. */
+enum { SX_CONV_X = 1, SX_CONV_Y = 2, SX_CONV_Z = 4, SX_VISC = 8, SX_ALL = 15 };
+
+/* precision of the flux arithmetic (state and RK registers are FP64). */
+enum { SX_FP64 = 0, SX_FP32_FLUX = 1 };
+
+typedef struct {
+    int nx, ny, nz;           /* interior nodes */
+    double lx, ly, lz;        /* domain lengths (x, z uniform: dx = lx/nx) */
+    double y0;                /* first node of a uniform y grid */
+    int ymap;                 /* SX_Y_* */
+    double beta;              /* tanh stretching parameter */
+    int bc[6];                /* x-lo, x-hi, y-lo, y-hi, z-lo, z-hi: SX_BC_* */
+} sx_grid;
+
+typedef struct {
+    double gamma;             /* ratio of specific heats */
+    double mach;              /* reference Mach number */
+    double reynolds;          /* reference Reynolds number */
+    double prandtl;
+    double visc_exp;          /* mu = T^visc_exp / Re */
+    double t_wall;            /* isothermal wall temperature */
+} sx_gas;
+
+typedef struct {
+    int central_order;        /* 2, 4, 6, 8 */
+    int weno_order;           /* 1, 3, 5 */
+    int visc_order;           /* must equal central_order in this build */
+    int sensor;               /* 0 off (pure central), 1 Ducros hybrid */
+    double sensor_thr;        /* WENO where max sensor over the stencil > thr */
+    double sensor_eps;        /* epsilon of the sensor denominator */
+    double weno_eps;          /* epsilon of the WENO weights */
+    int precision;            /* SX_FP64 or SX_FP32_FLUX */
+} sx_scheme;
+
+typedef struct {
+    int ng;                   /* ghost layers */
+    int ox;                   /* x offset of interior column 0 in a row */
+    long long px, py, pz;     /* padded extents: row, plane, volume pitch */
+    long long var_stride;     /* doubles between variables (= px*py*pz) */
+    long long elems;          /* doubles of one ghosted state (5*var_stride) */
+    long long interior;       /* nx*ny*nz */
+} sx_layout;
+
+/* Diagnostics (Section 3.2 reductions; cell volume dx * y_eta * dz). */
+typedef struct {
+    double mass;              /* sum V rho */
+    double momentum[3];       /* sum V rho u_i */
+    double energy;            /* sum V rho E */
+    double kinetic;           /* sum V rho |u|^2 / 2 */
+    double max_mach;
+    double min_rho;
+    double min_p;
+    double nonfinite;         /* interior nodes with a non-finite variable */
+    double nonphysical;       /* nodes with rho <= 0 or p <= 0 */
+    double residual_rhou;     /* sum over nodes of R_rhou^2 (if R given) */
+    double weno_fraction[3];  /* fraction of WENO faces per direction */
+    double volume;            /* sum V */
+} sx_diag;
+
+typedef struct sx_handle sx_handle;
+
+/* Validates the description, computes the y metrics on the host (D1/D2 of
+ * the node coordinates, central order) and uploads them. Allocates only
+ * small library-owned device buffers (metrics, reduction scratch). On error
+ * *out is NULL. */
+int sx_init(const sx_grid* grid, const sx_gas* gas, const sx_scheme* scheme,
+            sx_handle** out);
+
+/* Frees library-owned memory. Safe on NULL. */
+void sx_finalize(sx_handle* h);
+
+/* Ghosted layout the caller must allocate (host pointer out). */
+int sx_get_layout(const sx_handle* h, sx_layout* out);
+
+/* Binds caller-owned device buffers and a HIP stream (hipStream_t, may be
+ * NULL for the default stream): W0 and W1 are two ghosted states of
+ * layout.elems doubles (W0 holds the initial state; W1 is the ping-pong
+ * partner and receives a copy of W0, ghosts included, so frozen Dirichlet
+ * ghosts live in both), Rprev is an interior array of 5*interior doubles
+ * (the low-storage RK register). 256-byte alignment is required. */
+int sx_bind(sx_handle* h, double* W0, double* W1, double* Rprev, void* stream);
+
+/* Index (0 or 1) of the bound buffer holding the current state. Each RK3
+ * step (three substeps) flips it. */
+int sx_current(const sx_handle* h, int* which);
+
+/* Fills the ghost layers of a ghosted state in place (periodic copies,
+ * wall reflection, extrapolation; frozen faces untouched). */
+int sx_fill_ghosts(sx_handle* h, double* W);
+
+/* R = dW/dt of state W restricted to the terms in term_mask (SX_CONV_X,
+ * SX_CONV_Y, SX_CONV_Z, SX_VISC). Fills the ghosts of W first (side effect).
+ * R is an interior array; W and R must not alias. */
+int sx_rhs(sx_handle* h, double* W, double* R, unsigned term_mask);
+
+/* One full RK3 step (three substeps) of the bound state with time step dt:
+ * per substep W <- W + dt (gamma_k R(W) + zeta_k Rprev), Rprev <- R(W), with
+ * the Wray coefficients gamma = (8/15, 5/12, 3/4), zeta = (0, -17/60, -5/12).
+ * Asynchronous; no host synchronisation. */
+int sx_rk3_step(sx_handle* h, double dt);
+
+/* CFL time step from the current bound state (synchronises the stream):
+ * dt = cfl / max over nodes of sum_d (|u_d|+c)/h_d
+ *      + 2 gamma mu/(rho Pr) sum_d 1/h_d^2. */
+int sx_compute_dt(sx_handle* h, double cfl, double* dt);
+
+/* Diagnostics of the current bound state (R may be NULL; if given, an
+ * interior array whose rho-u component gives residual_rhou). Synchronises
+ * the stream. Returns SX_ENONFINITE when nonfinite or nonphysical > 0
+ * (the struct is still filled). */
+int sx_diagnostics(sx_handle* h, const double* R, sx_diag* out);
+
+/* Kernel timing for measurement. When enabled, sx_rk3_step brackets every
+ * launch of the fused right-hand-side/update kernel with HIP events recorded
+ * on the bound stream. sx_timing_read synchronises the recorded events,
+ * returns how many launches were timed and their summed duration in
+ * milliseconds, and clears the record. Disabled by default. */
+int sx_timing_enable(sx_handle* h, int enable);
+int sx_timing_read(sx_handle* h, long long* launches, double* total_ms);
+
+/* Message of the last failing call on this handle ("" if none). */
+const char* sx_last_error(const sx_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

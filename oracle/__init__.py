@@ -114,6 +114,7 @@ def lib():
         L.orc_compute_dt.argtypes = [P, dp, ctypes.c_double]
         L.orc_compute_dt.restype = ctypes.c_double
         L.orc_diagnostics.argtypes = [P, dp, dp, dp]
+        L.orc_num_threads.restype = ctypes.c_int
         L.orc_fd_coeffs.argtypes = [ctypes.c_int, dp, dp]
         L.orc_weno_left.argtypes = [ctypes.c_int, ctypes.c_double, dp]
         L.orc_weno_left.restype = ctypes.c_double
@@ -245,3 +246,7 @@ def face_flux_1d(gamma, W8, central_order=6, weno_order=5, weno_eps=1e-6, use_we
     F = np.zeros(5)
     lib().orc_face_flux_1d(gamma, central_order, weno_order, weno_eps, int(use_weno), _dp(W8), _dp(F))
     return F
+
+
+def num_threads() -> int:
+    return lib().orc_num_threads()

@@ -23,6 +23,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define NV 5
 
@@ -1040,4 +1043,14 @@ void orc_diagnostics(const orc_params* p, double* W, const double* R, double* ou
     out[15] = pairwise(t, nint);
     free(t);
     ctx_free(&c);
+}
+
+/* Threads the OpenMP loops of this oracle use (1 without OpenMP). */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

@@ -58,6 +58,8 @@ double orc_compute_dt(const orc_params* p, double* W, double cfl);
 void   orc_diagnostics(const orc_params* p, double* W, const double* R,
                        double* out);
 
+int    orc_num_threads(void);
+
 /* 1-D building blocks exposed for the pin tests. */
 void   orc_fd_coeffs(int order, double* a, double* b);
 double orc_weno_left(int order, double eps, const double* v);

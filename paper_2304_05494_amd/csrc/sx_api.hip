@@ -1,0 +1,398 @@
+// sx_api.hip -- C ABI of the library (declared in include/sx.h).
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "sx_internal.h"
+
+struct sx_handle {
+    sx_grid grid;
+    sx_gas gas;
+    sx_scheme scheme;
+    sx_layout lay;
+    sx::KGrid kg;
+    sx::KGas kgas;
+    sx::KScheme ks;
+    double* d_metrics = nullptr;  // eta_y, eta_yy, y_eta  (3*ny)
+    double* d_scratch = nullptr;  // reduction partials + results
+    double* W[2] = {nullptr, nullptr};
+    double* Rprev = nullptr;
+    hipStream_t st = nullptr;
+    int cur = 0;
+    bool bound = false;
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free;
+    std::string err;
+};
+
+namespace {
+
+int fail(sx_handle* h, int code, const char* msg)
+{
+    if (h) h->err = msg;
+    return code;
+}
+
+int hip_fail(sx_handle* h, hipError_t e, const char* where)
+{
+    if (h) {
+        char buf[256];
+        snprintf(buf, sizeof buf, "%s: %s", where, hipGetErrorString(e));
+        h->err = buf;
+    }
+    return SX_EHIP;
+}
+
+// y node coordinate of index j (ghost indices continue the mapping).
+double y_node(const sx_grid& g, int j)
+{
+    if (g.ymap == SX_Y_TANH2) {
+        const double eta = -1.0 + (2.0 * j + 1.0) / g.ny;
+        return 0.5 * g.ly * tanh(g.beta * eta) / tanh(g.beta);
+    }
+    if (g.ymap == SX_Y_TANH1) {
+        const double eta = (j + 0.5) / g.ny;
+        return g.ly * (1.0 - tanh(g.beta * (1.0 - eta)) / tanh(g.beta));
+    }
+    return g.y0 + j * (g.ly / g.ny);
+}
+
+// Host metrics: y_eta = D1(y), y_etaeta = D2(y) with the central stencil of
+// half-order L applied to the node coordinates (unit eta spacing).
+void host_metrics(const sx_grid& g, int L, double* y_eta, double* y_ee)
+{
+    static const double A[5][5] = {{0}, {0, 0.5}, {0, 2.0 / 3.0, -1.0 / 12.0},
+                                   {0, 0.75, -0.15, 1.0 / 60.0},
+                                   {0, 0.8, -0.2, 4.0 / 105.0, -1.0 / 280.0}};
+    static const double B[5][5] = {{0}, {0, 1.0}, {0, 4.0 / 3.0, -1.0 / 12.0},
+                                   {0, 1.5, -0.15, 1.0 / 90.0},
+                                   {0, 1.6, -0.2, 8.0 / 315.0, -1.0 / 560.0}};
+    for (int j = 0; j < g.ny; ++j) {
+        if (g.ymap == SX_Y_UNIFORM) {
+            y_eta[j] = g.ly / g.ny;
+            y_ee[j] = 0.0;
+            continue;
+        }
+        const double yc = y_node(g, j);
+        double d1 = 0.0, d2 = 0.0;
+        for (int l = 1; l <= L; ++l) {
+            const double yp = y_node(g, j + l), ym = y_node(g, j - l);
+            d1 += A[L][l] * (yp - ym);
+            d2 += B[L][l] * ((yp - 2.0 * yc) + ym);
+        }
+        y_eta[j] = d1;
+        y_ee[j] = d2;
+    }
+}
+
+bool valid_order(int o) { return o == 2 || o == 4 || o == 6 || o == 8; }
+
+hipError_t timed_begin(sx_handle* h, std::pair<hipEvent_t, hipEvent_t>* ev)
+{
+    if (!h->ev_free.empty()) {
+        *ev = h->ev_free.back();
+        h->ev_free.pop_back();
+    } else {
+        hipError_t e = hipEventCreate(&ev->first);
+        if (e != hipSuccess) return e;
+        e = hipEventCreate(&ev->second);
+        if (e != hipSuccess) return e;
+    }
+    return hipEventRecord(ev->first, h->st);
+}
+
+hipError_t timed_end(sx_handle* h, const std::pair<hipEvent_t, hipEvent_t>& ev)
+{
+    h->ev_used.push_back(ev);
+    return hipEventRecord(ev.second, h->st);
+}
+
+}  // namespace
+
+extern "C" {
+
+int sx_init(const sx_grid* grid, const sx_gas* gas, const sx_scheme* scheme, sx_handle** out)
+{
+    if (!out) return SX_EINVAL;
+    *out = nullptr;
+    if (!grid || !gas || !scheme) return SX_EINVAL;
+    const sx_grid& g = *grid;
+    const sx_scheme& s = *scheme;
+    if (!valid_order(s.central_order) || !valid_order(s.visc_order)) return SX_EINVAL;
+    if (s.weno_order != 1 && s.weno_order != 3 && s.weno_order != 5) return SX_EINVAL;
+    if (s.visc_order != s.central_order) return SX_EUNSUPPORTED;
+    if (s.sensor != 0) return SX_EUNSUPPORTED;
+    if (s.precision != SX_FP64) return SX_EUNSUPPORTED;
+    if (!(gas->gamma > 1.0) || !(gas->mach > 0.0) || !(gas->reynolds > 0.0) || !(gas->prandtl > 0.0))
+        return SX_EINVAL;
+    if (!(g.lx > 0.0) || !(g.ly > 0.0) || !(g.lz > 0.0)) return SX_EINVAL;
+    if (g.ymap < SX_Y_UNIFORM || g.ymap > SX_Y_TANH1) return SX_EINVAL;
+    if (g.ymap != SX_Y_UNIFORM && !(g.beta > 0.0)) return SX_EINVAL;
+    const int L = s.central_order / 2, Lv = s.visc_order / 2, r = (s.weno_order + 1) / 2;
+    int ng = L > Lv ? L : Lv;
+    if (r > ng) ng = r;
+    const int n[3] = {g.nx, g.ny, g.nz};
+    for (int d = 0; d < 3; ++d) {
+        if (n[d] < ng || n[d] > (1 << 20)) return SX_EINVAL;
+        for (int sd = 0; sd < 2; ++sd)
+            if (g.bc[2 * d + sd] < SX_BC_PERIODIC || g.bc[2 * d + sd] > SX_BC_FROZEN) return SX_EINVAL;
+        if ((g.bc[2 * d] == SX_BC_PERIODIC) != (g.bc[2 * d + 1] == SX_BC_PERIODIC)) return SX_EINVAL;
+    }
+
+    sx_handle* h = new sx_handle();
+    h->grid = g;
+    h->gas = *gas;
+    h->scheme = s;
+    sx_layout& lay = h->lay;
+    lay.ng = ng;
+    lay.ox = 16;
+    lay.px = ((lay.ox + g.nx + ng + 15) / 16) * 16;
+    lay.py = g.ny + 2 * ng;
+    lay.pz = g.nz + 2 * ng;
+    lay.var_stride = lay.px * lay.py * lay.pz;
+    lay.elems = 5 * lay.var_stride;
+    lay.interior = (long long)g.nx * g.ny * g.nz;
+    if (lay.elems >= (1LL << 40)) {
+        delete h;
+        return SX_EINVAL;
+    }
+
+    sx::KGrid& kg = h->kg;
+    kg.nx = g.nx;
+    kg.ny = g.ny;
+    kg.nz = g.nz;
+    kg.ng = ng;
+    kg.ox = lay.ox;
+    kg.sy = lay.px;
+    kg.sz = lay.px * lay.py;
+    kg.sv = lay.var_stride;
+    kg.base = ng * kg.sz + ng * kg.sy + lay.ox;
+    kg.nint = lay.interior;
+    for (int f = 0; f < 6; ++f) kg.bc[f] = g.bc[f];
+    kg.dx = g.lx / g.nx;
+    kg.dz = g.lz / g.nz;
+    kg.dxi = 1.0 / kg.dx;
+    kg.dzi = 1.0 / kg.dz;
+
+    sx::KGas& kgas = h->kgas;
+    kgas.gamma = gas->gamma;
+    kgas.gm1 = gas->gamma - 1.0;
+    kgas.gM2 = gas->gamma * gas->mach * gas->mach;
+    kgas.igM2 = 1.0 / kgas.gM2;
+    kgas.cp = 1.0 / (kgas.gm1 * gas->mach * gas->mach);
+    kgas.s = gas->visc_exp;
+    kgas.ire = 1.0 / gas->reynolds;
+    kgas.ipr = 1.0 / gas->prandtl;
+    kgas.t_wall = gas->t_wall;
+
+    sx::KScheme& ks = h->ks;
+    ks.L = L;
+    ks.Lv = Lv;
+    ks.r = r;
+    ks.sensor = s.sensor;
+    ks.sensor_thr = s.sensor_thr;
+    ks.sensor_eps = s.sensor_eps;
+    ks.weno_eps = s.weno_eps;
+
+    // metrics on the host, uploaded once
+    const int ny = g.ny;
+    double* hm = new double[3 * ny];
+    double* yee = new double[ny];
+    host_metrics(g, L, hm + 2 * ny, yee);
+    for (int j = 0; j < ny; ++j) {
+        const double ye = hm[2 * ny + j];
+        hm[j] = 1.0 / ye;
+        hm[ny + j] = -yee[j] / (ye * ye * ye);
+    }
+    delete[] yee;
+    hipError_t e = hipMalloc(&h->d_metrics, sizeof(double) * 3 * ny);
+    if (e == hipSuccess)
+        e = hipMemcpy(h->d_metrics, hm, sizeof(double) * 3 * ny, hipMemcpyHostToDevice);
+    delete[] hm;
+    if (e == hipSuccess)
+        e = hipMalloc(&h->d_scratch, sizeof(double) * (sx::kReduceBlocks + 1) * sx::kDiagVals);
+    if (e != hipSuccess) {
+        sx_finalize(h);
+        return e == hipErrorOutOfMemory ? SX_ENOMEM : SX_EHIP;
+    }
+    kg.eta_y = h->d_metrics;
+    kg.eta_yy = h->d_metrics + ny;
+    kg.y_eta = h->d_metrics + 2 * ny;
+    *out = h;
+    return SX_OK;
+}
+
+void sx_finalize(sx_handle* h)
+{
+    if (!h) return;
+    if (h->d_metrics) (void)hipFree(h->d_metrics);
+    if (h->d_scratch) (void)hipFree(h->d_scratch);
+    for (auto* v : {&h->ev_used, &h->ev_free})
+        for (auto& p : *v) {
+            (void)hipEventDestroy(p.first);
+            (void)hipEventDestroy(p.second);
+        }
+    delete h;
+}
+
+int sx_get_layout(const sx_handle* h, sx_layout* out)
+{
+    if (!h || !out) return SX_EINVAL;
+    *out = h->lay;
+    return SX_OK;
+}
+
+int sx_bind(sx_handle* h, double* W0, double* W1, double* Rprev, void* stream)
+{
+    if (!h) return SX_EINVAL;
+    if (!W0 || !W1 || !Rprev || W0 == W1) return fail(h, SX_EINVAL, "sx_bind: null or aliased buffer");
+    if (((uintptr_t)W0 | (uintptr_t)W1 | (uintptr_t)Rprev) & 255)
+        return fail(h, SX_EINVAL, "sx_bind: buffers must be 256-byte aligned");
+    h->W[0] = W0;
+    h->W[1] = W1;
+    h->Rprev = Rprev;
+    h->st = (hipStream_t)stream;
+    h->cur = 0;
+    hipError_t e = hipMemcpyAsync(W1, W0, sizeof(double) * h->lay.elems, hipMemcpyDeviceToDevice, h->st);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(Rprev, 0, sizeof(double) * 5 * h->lay.interior, h->st);
+    if (e != hipSuccess) return hip_fail(h, e, "sx_bind");
+    h->bound = true;
+    h->err.clear();
+    return SX_OK;
+}
+
+int sx_current(const sx_handle* h, int* which)
+{
+    if (!h || !which) return SX_EINVAL;
+    *which = h->cur;
+    return SX_OK;
+}
+
+int sx_fill_ghosts(sx_handle* h, double* W)
+{
+    if (!h) return SX_EINVAL;
+    if (!W) return fail(h, SX_EINVAL, "sx_fill_ghosts: null state");
+    hipError_t e = sx::launch_ghost_fill(h->kg, h->kgas, W, h->st);
+    if (e != hipSuccess) return hip_fail(h, e, "sx_fill_ghosts");
+    return SX_OK;
+}
+
+int sx_rhs(sx_handle* h, double* W, double* R, unsigned term_mask)
+{
+    if (!h) return SX_EINVAL;
+    if (!W || !R || W == R) return fail(h, SX_EINVAL, "sx_rhs: null or aliased buffer");
+    if (term_mask & ~(unsigned)SX_ALL) return fail(h, SX_EINVAL, "sx_rhs: unknown term bits");
+    hipError_t e = sx::launch_ghost_fill(h->kg, h->kgas, W, h->st);
+    if (e == hipSuccess) e = sx::launch_rhs(h->kg, h->kgas, h->ks, W, R, nullptr, nullptr, term_mask, h->st);
+    if (e != hipSuccess) return hip_fail(h, e, "sx_rhs");
+    return SX_OK;
+}
+
+int sx_rk3_step(sx_handle* h, double dt)
+{
+    static const double gk[3] = {8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0};
+    static const double zk[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
+    if (!h) return SX_EINVAL;
+    if (!h->bound) return fail(h, SX_ESTATE, "sx_rk3_step: no buffers bound");
+    if (!(dt > 0.0) || !isfinite(dt)) return fail(h, SX_EINVAL, "sx_rk3_step: dt must be positive");
+    for (int s = 0; s < 3; ++s) {
+        double* src = h->W[h->cur];
+        double* dst = h->W[1 - h->cur];
+        sx::StepCoef sc{dt * gk[s], dt * zk[s], s > 0 ? 1 : 0, s < 2 ? 1 : 0};
+        hipError_t e = sx::launch_ghost_fill(h->kg, h->kgas, src, h->st);
+        std::pair<hipEvent_t, hipEvent_t> ev{};
+        if (e == hipSuccess && h->timing) e = timed_begin(h, &ev);
+        if (e == hipSuccess)
+            e = sx::launch_rhs(h->kg, h->kgas, h->ks, src, dst, h->Rprev, &sc, SX_ALL, h->st);
+        if (e == hipSuccess && h->timing) e = timed_end(h, ev);
+        if (e != hipSuccess) return hip_fail(h, e, "sx_rk3_step");
+        h->cur = 1 - h->cur;
+    }
+    return SX_OK;
+}
+
+int sx_compute_dt(sx_handle* h, double cfl, double* dt)
+{
+    if (!h || !dt) return SX_EINVAL;
+    if (!h->bound) return fail(h, SX_ESTATE, "sx_compute_dt: no buffers bound");
+    if (!(cfl > 0.0)) return fail(h, SX_EINVAL, "sx_compute_dt: cfl must be positive");
+    const int nb = sx::kReduceBlocks;
+    double rate = 0.0;
+    hipError_t e = sx::launch_max_rate(h->kg, h->kgas, h->W[h->cur], h->d_scratch, nb, h->st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&rate, h->d_scratch + nb, sizeof(double), hipMemcpyDeviceToHost, h->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+    if (e != hipSuccess) return hip_fail(h, e, "sx_compute_dt");
+    if (!(rate > 0.0) || !isfinite(rate)) return fail(h, SX_ENONFINITE, "sx_compute_dt: rate not finite");
+    *dt = cfl / rate;
+    return SX_OK;
+}
+
+int sx_diagnostics(sx_handle* h, const double* R, sx_diag* out)
+{
+    if (!h || !out) return SX_EINVAL;
+    if (!h->bound) return fail(h, SX_ESTATE, "sx_diagnostics: no buffers bound");
+    const int nb = sx::kReduceBlocks;
+    double v[sx::kDiagVals];
+    hipError_t e = sx::launch_diagnostics(h->kg, h->kgas, h->ks, h->W[h->cur], R, h->d_scratch, nb, h->st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(v, h->d_scratch + (long long)nb * sx::kDiagVals, sizeof v,
+                           hipMemcpyDeviceToHost, h->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+    if (e != hipSuccess) return hip_fail(h, e, "sx_diagnostics");
+    out->mass = v[0];
+    out->momentum[0] = v[1];
+    out->momentum[1] = v[2];
+    out->momentum[2] = v[3];
+    out->energy = v[4];
+    out->kinetic = v[5];
+    out->max_mach = v[6];
+    out->min_rho = v[7];
+    out->min_p = v[8];
+    out->nonfinite = v[9];
+    out->nonphysical = v[10];
+    out->residual_rhou = R ? v[11] : 0.0;
+    out->weno_fraction[0] = v[12];
+    out->weno_fraction[1] = v[13];
+    out->weno_fraction[2] = v[14];
+    out->volume = v[15];
+    if (v[9] > 0.0 || v[10] > 0.0) return fail(h, SX_ENONFINITE, "sx_diagnostics: non-finite or non-physical state");
+    return SX_OK;
+}
+
+int sx_timing_enable(sx_handle* h, int enable)
+{
+    if (!h) return SX_EINVAL;
+    h->timing = enable != 0;
+    return SX_OK;
+}
+
+int sx_timing_read(sx_handle* h, long long* launches, double* total_ms)
+{
+    if (!h || !launches || !total_ms) return SX_EINVAL;
+    double tot = 0.0;
+    for (auto& p : h->ev_used) {
+        float ms = 0.0f;
+        hipError_t e = hipEventSynchronize(p.second);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, p.first, p.second);
+        if (e != hipSuccess) return hip_fail(h, e, "sx_timing_read");
+        tot += ms;
+    }
+    *launches = (long long)h->ev_used.size();
+    *total_ms = tot;
+    h->ev_free.insert(h->ev_free.end(), h->ev_used.begin(), h->ev_used.end());
+    h->ev_used.clear();
+    return SX_OK;
+}
+
+const char* sx_last_error(const sx_handle* h)
+{
+    return h ? h->err.c_str() : "null handle";
+}
+
+}  // extern "C"

@@ -1,0 +1,89 @@
+// sx_internal.h -- shared definitions of the HIP library (device + host).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sx.h"
+
+namespace sx {
+
+constexpr int NV = 5;
+
+// Kernel-side description of one grid block. Passed by value.
+struct KGrid {
+    int nx, ny, nz, ng, ox;
+    long long sy, sz, sv;       // strides of y, z and variable (doubles)
+    long long base;             // offset of interior node (0,0,0)
+    long long nint;             // nx*ny*nz
+    int bc[6];
+    double dxi, dzi;            // 1/dx, 1/dz
+    double dx, dz;
+    const double* eta_y;        // [ny] 1 / y_eta
+    const double* eta_yy;       // [ny] -y_etaeta / y_eta^3
+    const double* y_eta;        // [ny]
+};
+
+struct KGas {
+    double gamma, gm1;          // gamma, gamma - 1
+    double gM2;                 // gamma M^2   (T = gM2 p / rho)
+    double igM2;                // 1/(gamma M^2)
+    double cp;                  // 1/((gamma-1) M^2)
+    double s;                   // viscosity exponent
+    double ire;                 // 1/Re
+    double ipr;                 // 1/Pr
+    double t_wall;
+};
+
+struct KScheme {
+    int L;                      // central half-order
+    int Lv;                     // viscous half-order
+    int r;                      // WENO half-width
+    int sensor;
+    double sensor_thr, sensor_eps, weno_eps;
+};
+
+// Central first-derivative weights a_l (D1 f = sum a_l (f_{+l} - f_{-l})) and
+// narrow second-derivative weights b_l (D2 f = sum b_l (f_{+l} - 2 f + f_{-l}))
+// of order 2S on a unit-spaced grid (Taylor-series stencils).
+template <int S> struct Coef;
+template <> struct Coef<1> {
+    static constexpr double a[2] = {0.0, 0.5};
+    static constexpr double b[2] = {0.0, 1.0};
+};
+template <> struct Coef<2> {
+    static constexpr double a[3] = {0.0, 2.0 / 3.0, -1.0 / 12.0};
+    static constexpr double b[3] = {0.0, 4.0 / 3.0, -1.0 / 12.0};
+};
+template <> struct Coef<3> {
+    static constexpr double a[4] = {0.0, 3.0 / 4.0, -3.0 / 20.0, 1.0 / 60.0};
+    static constexpr double b[4] = {0.0, 3.0 / 2.0, -3.0 / 20.0, 1.0 / 90.0};
+};
+template <> struct Coef<4> {
+    static constexpr double a[5] = {0.0, 4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280.0};
+    static constexpr double b[5] = {0.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+};
+
+// RK3 (Wray) coefficients of one substep, premultiplied by dt.
+struct StepCoef {
+    double cg;      // dt * gamma_k
+    double cz;      // dt * zeta_k
+    int read_prev;  // zeta_k != 0
+    int write_prev; // another substep follows
+};
+
+// ---- host-side launchers (one per translation unit) --------------------
+hipError_t launch_ghost_fill(const KGrid& g, const KGas& gas, double* W, hipStream_t st);
+hipError_t launch_rhs(const KGrid& g, const KGas& gas, const KScheme& sc, const double* W,
+                      double* out, double* Rprev, const StepCoef* step, unsigned mask,
+                      hipStream_t st);
+hipError_t launch_diagnostics(const KGrid& g, const KGas& gas, const KScheme& sc,
+                              const double* W, const double* R, double* scratch,
+                              int nscratch_blocks, hipStream_t st);
+hipError_t launch_max_rate(const KGrid& g, const KGas& gas, const double* W, double* scratch,
+                           int nscratch_blocks, hipStream_t st);
+
+constexpr int kReduceBlocks = 1024;   // partial-result slots of the reductions
+constexpr int kDiagVals = 16;
+
+}  // namespace sx

@@ -1,0 +1,168 @@
+// sx_reduce.hip -- deterministic FP64 reductions: diagnostics (the paper's
+// compute_residual sum reduction, Table 2) and the CFL rate (compute_dt max
+// reduction). Two passes with a fixed point-to-thread assignment and fixed
+// tree order, so repeated calls give bitwise-identical results.
+#include "sx_internal.h"
+
+namespace sx {
+
+namespace {
+
+constexpr int RB = 256;  // threads per reduction block
+
+enum {
+    D_MASS = 0, D_MX, D_MY, D_MZ, D_E, D_KE, D_MACH, D_RMIN, D_PMIN, D_NONFIN, D_NONPHYS,
+    D_RES, D_WX, D_WY, D_WZ, D_VOL
+};
+
+__device__ __forceinline__ double combine(int q, double a, double b)
+{
+    if (q == D_MACH) return fmax(a, b);
+    if (q == D_RMIN || q == D_PMIN) return fmin(a, b);
+    return a + b;
+}
+
+__device__ __forceinline__ double neutral(int q)
+{
+    if (q == D_MACH) return 0.0;
+    if (q == D_RMIN || q == D_PMIN) return __builtin_huge_val();
+    return 0.0;
+}
+
+__global__ void __launch_bounds__(RB) k_diag_partial(KGrid g, KGas gas, const double* __restrict__ W,
+                                                     const double* __restrict__ R,
+                                                     double* __restrict__ part)
+{
+    __shared__ double red[kDiagVals][RB];
+    double acc[kDiagVals];
+#pragma unroll
+    for (int q = 0; q < kDiagVals; ++q) acc[q] = neutral(q);
+    const long long T = (long long)gridDim.x * RB;
+    for (long long m = (long long)blockIdx.x * RB + threadIdx.x; m < g.nint; m += T) {
+        const int i = (int)(m % g.nx);
+        const long long jk = m / g.nx;
+        const int j = (int)(jk % g.ny);
+        const int k = (int)(jk / g.ny);
+        const long long n = g.base + (long long)k * g.sz + (long long)j * g.sy + i;
+        const double vol = g.dx * g.y_eta[j] * g.dz;
+        double w[NV];
+        bool fin = true;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            w[v] = W[v * g.sv + n];
+            fin = fin && isfinite(w[v]);
+        }
+        acc[D_VOL] += vol;
+        if (R) {
+            const double r = R[g.nint + m];
+            acc[D_RES] += r * r;
+        }
+        acc[D_MASS] += vol * w[0];
+        acc[D_MX] += vol * w[1];
+        acc[D_MY] += vol * w[2];
+        acc[D_MZ] += vol * w[3];
+        acc[D_E] += vol * w[4];
+        if (!fin) {
+            acc[D_NONFIN] += 1.0;
+            continue;
+        }
+        const double ri = 1.0 / w[0];
+        const double u = w[1] * ri, v = w[2] * ri, ww = w[3] * ri;
+        const double q2 = u * u + v * v + ww * ww;
+        const double p = gas.gm1 * (w[4] - 0.5 * w[0] * q2);
+        acc[D_KE] += vol * (0.5 * w[0] * q2);
+        if (!(w[0] > 0.0) || !(p > 0.0)) acc[D_NONPHYS] += 1.0;
+        acc[D_RMIN] = fmin(acc[D_RMIN], w[0]);
+        acc[D_PMIN] = fmin(acc[D_PMIN], p);
+        if (w[0] > 0.0 && p > 0.0) acc[D_MACH] = fmax(acc[D_MACH], sqrt(q2 * w[0] / (gas.gamma * p)));
+    }
+#pragma unroll
+    for (int q = 0; q < kDiagVals; ++q) red[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int s = RB / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+#pragma unroll
+            for (int q = 0; q < kDiagVals; ++q)
+                red[q][threadIdx.x] = combine(q, red[q][threadIdx.x], red[q][threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < kDiagVals) part[(long long)blockIdx.x * kDiagVals + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(RB) k_final(const double* __restrict__ part, int nblk, int nvals,
+                                              int mode, double* __restrict__ res)
+{
+    // mode 0: diagnostics combine rules per value; mode 1: max of value 0
+    __shared__ double red[RB];
+    for (int q = 0; q < nvals; ++q) {
+        const int rule = mode == 1 ? D_MACH : q;
+        double a = neutral(rule);
+        for (int b = threadIdx.x; b < nblk; b += RB) a = combine(rule, a, part[(long long)b * nvals + q]);
+        red[threadIdx.x] = a;
+        __syncthreads();
+        for (int s = RB / 2; s > 0; s >>= 1) {
+            if (threadIdx.x < s) red[threadIdx.x] = combine(rule, red[threadIdx.x], red[threadIdx.x + s]);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) res[q] = red[0];
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(RB) k_rate_partial(KGrid g, KGas gas, const double* __restrict__ W,
+                                                     double* __restrict__ part)
+{
+    __shared__ double red[RB];
+    double a = 0.0;
+    const long long T = (long long)gridDim.x * RB;
+    for (long long m = (long long)blockIdx.x * RB + threadIdx.x; m < g.nint; m += T) {
+        const int i = (int)(m % g.nx);
+        const long long jk = m / g.nx;
+        const int j = (int)(jk % g.ny);
+        const int k = (int)(jk / g.ny);
+        const long long n = g.base + (long long)k * g.sz + (long long)j * g.sy + i;
+        const double rho = W[n];
+        const double ri = 1.0 / rho;
+        const double u = W[g.sv + n] * ri, v = W[2 * g.sv + n] * ri, w = W[3 * g.sv + n] * ri;
+        const double p = gas.gm1 * (W[4 * g.sv + n] - 0.5 * rho * (u * u + v * v + w * w));
+        const double cs = sqrt(gas.gamma * p * ri);
+        const double T_ = gas.gM2 * p * ri;
+        const double mu = pow(T_, gas.s) * gas.ire;
+        const double hy = g.y_eta[j];
+        const double conv = (fabs(u) + cs) * g.dxi + (fabs(v) + cs) / hy + (fabs(w) + cs) * g.dzi;
+        const double visc = 2.0 * gas.gamma * mu * ri * gas.ipr *
+                            (g.dxi * g.dxi + 1.0 / (hy * hy) + g.dzi * g.dzi);
+        a = fmax(a, conv + visc);
+    }
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int s = RB / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+}  // namespace
+
+// scratch: nblk*kDiagVals partials followed by kDiagVals results.
+hipError_t launch_diagnostics(const KGrid& g, const KGas& gas, const KScheme&, const double* W,
+                              const double* R, double* scratch, int nblk, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_diag_partial, dim3(nblk), dim3(RB), 0, st, g, gas, W, R, scratch);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(RB), 0, st, scratch, nblk, kDiagVals, 0,
+                       scratch + (long long)nblk * kDiagVals);
+    return hipGetLastError();
+}
+
+// scratch: nblk partials followed by one result (largest CFL rate).
+hipError_t launch_max_rate(const KGrid& g, const KGas& gas, const double* W, double* scratch,
+                           int nblk, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_rate_partial, dim3(nblk), dim3(RB), 0, st, g, gas, W, scratch);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(RB), 0, st, scratch, nblk, 1, 1, scratch + nblk);
+    return hipGetLastError();
+}
+
+}  // namespace sx

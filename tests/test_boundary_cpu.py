@@ -1,0 +1,99 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function
+include/sx.h declares, the binding's structs match the header, and invalid
+descriptions are rejected before any device call (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2304_05494_amd import inputs, sx
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "sx.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sx_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_exports():
+    assert declared_functions() == sorted(sx.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(sx.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_struct_layouts_match_the_c_header(tmp_path):
+    """Compile the header with gcc and compare every field offset and struct
+    size with the ctypes mirrors used by the binding."""
+    import subprocess
+    structs = [sx.sx_grid, sx.sx_gas, sx.sx_scheme, sx.sx_layout, sx.sx_diag]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sx.h"', 'int main(void){']
+    for st in structs:
+        n = st.__name__
+        lines.append(f'printf("{n} size %zu\\n", sizeof({n}));')
+        for f, _ in st._fields_:
+            lines.append(f'printf("{n} {f} %zu\\n", offsetof({n}, {f}));')
+    lines.append('return 0;}')
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for st in structs:
+        n = st.__name__
+        assert got[(n, "size")] == ctypes.sizeof(st), n
+        for f, _ in st._fields_:
+            assert got[(n, f)] == getattr(st, f).offset, (n, f)
+
+
+def _init(case, **patch):
+    L = sx.load()
+    g, gas, sc = sx.make_structs(case)
+    for k, v in patch.items():
+        for s in (g, gas, sc):
+            if hasattr(s, k):
+                setattr(s, k, v)
+    h = ctypes.c_void_p()
+    rc = L.sx_init(ctypes.byref(g), ctypes.byref(gas), ctypes.byref(sc), ctypes.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("patch,code", [
+    ({"central_order": 5}, sx.SX_EINVAL),
+    ({"central_order": 10}, sx.SX_EINVAL),
+    ({"visc_order": 3}, sx.SX_EINVAL),
+    ({"weno_order": 7}, sx.SX_EINVAL),
+    ({"nx": 2}, sx.SX_EINVAL),
+    ({"gamma": 1.0}, sx.SX_EINVAL),
+    ({"lx": 0.0}, sx.SX_EINVAL),
+    ({"ymap": 9}, sx.SX_EINVAL),
+])
+def test_invalid_descriptions_rejected_without_device(patch, code):
+    rc, h = _init(inputs.tgv_case(16), **patch)
+    assert rc == code
+    assert not h.value
+
+
+def test_unpaired_periodic_face_rejected():
+    case = inputs.tgv_case(16)
+    L = sx.load()
+    g, gas, sc = sx.make_structs(case)
+    g.bc[0] = sx.SX_BC_WALL      # x-lo wall with x-hi periodic
+    h = ctypes.c_void_p()
+    assert L.sx_init(ctypes.byref(g), ctypes.byref(gas), ctypes.byref(sc), ctypes.byref(h)) == sx.SX_EINVAL
+
+
+def test_null_arguments():
+    L = sx.load()
+    h = ctypes.c_void_p()
+    assert L.sx_init(None, None, None, ctypes.byref(h)) == sx.SX_EINVAL
+    assert L.sx_rk3_step(None, ctypes.c_double(1.0)) == sx.SX_EINVAL
+    assert L.sx_last_error(None) == b"null handle"
+    L.sx_finalize(None)
