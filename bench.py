@@ -39,7 +39,25 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle timing (profiling runs)")
     ap.add_argument("--cpu-sample-steps", type=int, default=1)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain device copy of 2 GiB (counter calibration)")
     return ap.parse_args()
+
+
+def calibrate_copy():
+    """A plain copy of known size: 2 GiB read + 2 GiB written, three times.
+    Its FETCH_SIZE / WRITE_SIZE counters give the scale factor between what
+    those counters report and bytes actually moved."""
+    import torch
+    n = (2 << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "copy", "bytes_read_per_launch": n * 8,
+                      "bytes_written_per_launch": n * 8, "launches": 3}), flush=True)
 
 
 def load_traffic(kernel: str):
@@ -80,6 +98,9 @@ def cpu_baseline(case, Wn, dt, steps):
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))

@@ -5,86 +5,40 @@
 //
 // Mapping (gfx950, wave64): a workgroup owns a TX x TY column tile (lanes
 // along contiguous x, so every row load is coalesced) and marches along z
-// over a chunk of planes. Each iteration stages two planes of primitives
-// (rho, u, v, w, T) with an S-wide halo in LDS:
-//   * the arrival plane k+S feeds per-column register queues: primitives
-//     for the z stencils, and the in-plane derivatives (D_x w, D_y w,
-//     D_x u + D_y v) whose z-derivatives are the mixed viscous terms;
-//   * the output plane k feeds the in-plane (x, y) stencils.
+// over a chunk of planes. Each iteration stages two planes in LDS with an
+// S-wide halo:
+//   * the arrival plane k+S (u, v, w) feeds per-column register queues of
+//     in-plane derivatives (D_x w, D_y w, D_x u + D_y v) whose z-derivatives
+//     are the mixed viscous terms; the column's own primitives at k+S enter
+//     a register queue that serves every z stencil;
+//   * the output plane k (rho, u, v, w, T, p as 48-byte records read with
+//     128-bit LDS loads, bank-conflict free) feeds the x and y stencils.
 // The y-derivatives of u and v are also computed over the x-halo columns
-// into a small LDS row so D_x(D_y .) costs one short stencil. The RHS of a
-// node never leaves registers: in update mode the kernel applies the RK3
-// substep and writes the new state and the RK register directly, so HBM
-// traffic per substep is one read of W, one write of W' and the RK register.
+// into a small LDS row so D_x(D_y .) costs one short stencil. Work at the
+// output node runs in x, y, z phases separated by scheduling barriers so
+// only one direction's stencil values are live at a time (two waves per
+// SIMD). The RHS of a node never leaves registers: in update mode the
+// kernel applies the RK3 substep and writes the new state and the RK
+// register, so HBM traffic per substep is one read of W, one write of W'
+// and the RK register.
+#include <stdlib.h>
+#include <string.h>
+
 #include "sx_internal.h"
 
 namespace sx {
 
-struct Prim {
-    double r, u, v, w, T;
-};
-
-__device__ __forceinline__ Prim load_prim(const double* __restrict__ W, long long n, long long sv,
-                                          const KGas& gas)
+// 1/x: hardware reciprocal refined by two Newton steps (about 1 ulp).
+__device__ __forceinline__ double rcp(double x)
 {
-    Prim q;
-    const double rho = W[n];
-    const double ri = 1.0 / rho;
-    q.r = rho;
-    q.u = W[n + sv] * ri;
-    q.v = W[n + 2 * sv] * ri;
-    q.w = W[n + 3 * sv] * ri;
-    const double p = gas.gm1 * (W[n + 4 * sv] - 0.5 * rho * (q.u * q.u + q.v * q.v + q.w * q.w));
-    q.T = gas.gM2 * p * ri;
-    return q;
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
 }
 
-// Convective derivative along one direction from 2S+1 nodes (centre S),
-// pair-difference form of the split flux:
-//   F_{i+1/2} - F_{i-1/2} = sum_l 2 a_l [P_l(i) - P_l(i-l)],
-//   P_l(n) = 1/8 (rho_n + rho_{n+l})(ud_n + ud_{n+l})(phi_n + phi_{n+l}),
-// phi in {1, u, v, w, H}, pressure 1/2 (p_n + p_{n+l}) in the D-momentum.
-// Subtracts scale * (flux difference) from acc.
-template <int S, int D>
-__device__ __forceinline__ void conv_dir(const double (&r)[2 * S + 1], const double (&u)[2 * S + 1],
-                                         const double (&v)[2 * S + 1], const double (&w)[2 * S + 1],
-                                         const double (&T)[2 * S + 1], const KGas& gas, double scale,
-                                         double (&acc)[NV])
-{
-    double p[2 * S + 1], H[2 * S + 1];
-#pragma unroll
-    for (int t = 0; t < 2 * S + 1; ++t) {
-        p[t] = r[t] * T[t] * gas.igM2;
-        H[t] = gas.cp * T[t] + 0.5 * (u[t] * u[t] + v[t] * v[t] + w[t] * w[t]);
-    }
-    const double(&ud)[2 * S + 1] = D == 0 ? u : (D == 1 ? v : w);
-    double f0 = 0.0, f1 = 0.0, f2 = 0.0, f3 = 0.0, f4 = 0.0, fp = 0.0;
-#pragma unroll
-    for (int l = 1; l <= S; ++l) {
-        const double cl = 0.25 * Coef<S>::a[l];
-#pragma unroll
-        for (int side = 0; side < 2; ++side) {
-            const int A = side == 0 ? S : S - l;
-            const int B = A + l;
-            const double c = side == 0 ? cl : -cl;
-            const double mf = c * (r[A] + r[B]) * (ud[A] + ud[B]);
-            f0 += 2.0 * mf;
-            f1 += mf * (u[A] + u[B]);
-            f2 += mf * (v[A] + v[B]);
-            f3 += mf * (w[A] + w[B]);
-            f4 += mf * (H[A] + H[B]);
-            fp += 4.0 * c * (p[A] + p[B]);
-        }
-    }
-    if (D == 0) f1 += fp;
-    if (D == 1) f2 += fp;
-    if (D == 2) f3 += fp;
-    acc[0] -= scale * f0;
-    acc[1] -= scale * f1;
-    acc[2] -= scale * f2;
-    acc[3] -= scale * f3;
-    acc[4] -= scale * f4;
-}
+__device__ __forceinline__ void sched_fence() { __builtin_amdgcn_sched_barrier(0); }
 
 template <int S>
 __device__ __forceinline__ double d1(const double (&f)[2 * S + 1])
@@ -104,17 +58,128 @@ __device__ __forceinline__ double d2(const double (&f)[2 * S + 1])
     return s;
 }
 
+// Node values along one stencil direction.
+struct Node {
+    double r, u, v, w, T, p, H;
+};
+
+__device__ __forceinline__ Node node_from_record(const double* __restrict__ so,
+                                                 const double* __restrict__ sH, int q)
+{
+    const double2* rec = reinterpret_cast<const double2*>(so + 6 * q);
+    const double2 a = rec[0], b = rec[1], e = rec[2];
+    return Node{a.x, a.y, b.x, b.y, e.x, e.y, sH[q]};
+}
+
+// One direction of the output node, streaming the stencil pairs l = 1..S
+// so only the centre and the two nodes at distance l are live: adds the
+// split-form convective derivative (pair-difference form, see conv_dir)
+// to acc and returns first derivatives gd = (u, v, w, T)_n and the pure
+// second derivatives dd = (u, v, w, T)_nn (sc: metric 1/h or eta_y;
+// sc2 = sc^2; scy = eta_yy along y, 0 otherwise).
+template <int S, int D, bool CONV, bool VISC, typename Get>
+__device__ __forceinline__ void stencil_dir(Get get, double sc, double sc2, double scy,
+                                            double (&acc)[NV], double (&gd)[4], double (&dd)[4])
+{
+    const Node C = get(0);
+    double f0 = 0.0, f1 = 0.0, f2 = 0.0, f3 = 0.0, f4 = 0.0, fp = 0.0;
+    double s1[4] = {0.0, 0.0, 0.0, 0.0}, s2[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int l = 1; l <= S; ++l) {
+        const Node M = get(-l), P = get(l);
+        if (CONV) {
+            const double cl = 0.25 * Coef<S>::a[l];
+            const double udC = D == 0 ? C.u : (D == 1 ? C.v : C.w);
+            const double udP = D == 0 ? P.u : (D == 1 ? P.v : P.w);
+            const double udM = D == 0 ? M.u : (D == 1 ? M.v : M.w);
+            const double mp = cl * (C.r + P.r) * (udC + udP);    // pair (C, P), +
+            const double mm = cl * (M.r + C.r) * (udM + udC);    // pair (M, C), -
+            f0 += 2.0 * (mp - mm);
+            f1 += mp * (C.u + P.u) - mm * (M.u + C.u);
+            f2 += mp * (C.v + P.v) - mm * (M.v + C.v);
+            f3 += mp * (C.w + P.w) - mm * (M.w + C.w);
+            f4 += mp * (C.H + P.H) - mm * (M.H + C.H);
+            fp += (4.0 * cl) * (P.p - M.p);
+        }
+        if (VISC) {
+            const double al = Coef<S>::a[l], bl = Coef<S>::b[l];
+            s1[0] += al * (P.u - M.u);
+            s1[1] += al * (P.v - M.v);
+            s1[2] += al * (P.w - M.w);
+            s1[3] += al * (P.T - M.T);
+            s2[0] += bl * ((P.u - 2.0 * C.u) + M.u);
+            s2[1] += bl * ((P.v - 2.0 * C.v) + M.v);
+            s2[2] += bl * ((P.w - 2.0 * C.w) + M.w);
+            s2[3] += bl * ((P.T - 2.0 * C.T) + M.T);
+        }
+    }
+    if (CONV) {
+        if (D == 0) f1 += fp;
+        if (D == 1) f2 += fp;
+        if (D == 2) f3 += fp;
+        acc[0] -= sc * f0;
+        acc[1] -= sc * f1;
+        acc[2] -= sc * f2;
+        acc[3] -= sc * f3;
+        acc[4] -= sc * f4;
+    }
+    if (VISC) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            gd[q] = sc * s1[q];
+            dd[q] = __builtin_fma(sc2, s2[q], scy * s1[q]);
+        }
+    }
+}
+
+// Linear viscous pieces of one direction d, consumed at once:
+// mu (u_i)_dd (+ mu/3 (u_d)_dd into momentum d), k T_dd, and their work
+// u_i (...) into the energy.
+template <int D>
+__device__ __forceinline__ void visc_linear(const double (&dd)[4], double mu, double kc, double uc,
+                                            double vc, double wc, double (&acc)[NV])
+{
+    const double o3 = 1.0 / 3.0;
+    double a0 = mu * dd[0], a1 = mu * dd[1], a2 = mu * dd[2];
+    if (D == 0) a0 += (mu * o3) * dd[0];
+    if (D == 1) a1 += (mu * o3) * dd[1];
+    if (D == 2) a2 += (mu * o3) * dd[2];
+    acc[1] += a0;
+    acc[2] += a1;
+    acc[3] += a2;
+    acc[4] += uc * a0 + vc * a1 + wc * a2 + kc * dd[3];
+}
+
+// Conserved values of up to NPT halo points of one plane, fetched into
+// registers one iteration ahead of their use.
+template <int NPT>
+struct PlaneFetch {
+    double q[NPT][5];
+};
+
+// One workgroup (TX x TY columns, one wave per SIMD) marches a column tile
+// along z. LDS holds: the arrival plane k+S (u, v, w with halo), the output
+// plane k (records rho,u,v,w,T,p + enthalpy, with halo), D_y u and D_y v
+// over the x-halo columns, and a ring of the last 2S+1 planes of every
+// column's own primitives (rho,u,v,w,T,H) that serves the z stencils. The
+// in-plane derivatives whose z-derivatives are the mixed viscous terms stay
+// in register queues. Global loads of iteration k+1 are issued before the
+// compute of iteration k, and the stores of iteration k are issued after the
+// staging of iteration k+1, so neither waits on the other.
 template <int S, int TX, int TY, bool UPD>
-__global__ void __attribute__((amdgpu_flat_work_group_size(TX * TY, TX * TY)))
+__global__ void __attribute__((amdgpu_flat_work_group_size(TX * TY, TX * TY), amdgpu_waves_per_eu(1)))
 k_rhs_central(const double* __restrict__ W, double* __restrict__ out, double* __restrict__ Rp,
               KGrid g, KGas gas, StepCoef sc, unsigned mask, int kc)
 {
     constexpr int NT = TX * TY;
     constexpr int HX = TX + 2 * S, HY = TY + 2 * S, HP = HX * HY;
+    constexpr int NPT = (HP + NT - 1) / NT;
     constexpr int Q = 2 * S + 1;
-    __shared__ double sa[5][HP];      // arrival plane k+S
-    __shared__ double so[5][HP];      // output plane k
-    __shared__ double gyl[2][TY][HX]; // D_y u, D_y v of plane k over x-halo columns
+    __shared__ double sa[3][HP];                                  // arrival plane: u, v, w
+    __shared__ __attribute__((aligned(16))) double so[6 * HP];    // output plane records
+    __shared__ double sH[HP];                                     // output plane enthalpy
+    __shared__ double gyl[2][TY][HX];                             // D_y u, D_y v of plane k
+    __shared__ __attribute__((aligned(16))) double zring[Q * NT * 6];  // column records
 
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
@@ -127,189 +192,315 @@ k_rhs_central(const double* __restrict__ W, double* __restrict__ out, double* __
     const double ey = active ? g.eta_y[j] : 0.0;
     const double eyy = active ? g.eta_yy[j] : 0.0;
     const double dxi = g.dxi, dzi = g.dzi;
-
-    double zq[5][Q];  // primitives of this column, planes k-S .. k+S
-    double mq[3][Q];  // D_x w, D_y w, D_x u + D_y v of this column
+    const long long col = g.base + (long long)j * g.sy + i;   // this column at k = 0
+    constexpr int NGY = (TY * HX + NT - 1) / NT;
+    double egy[NGY];                                          // eta_y of the D_y rows
 #pragma unroll
-    for (int t = 0; t < Q; ++t) {
-#pragma unroll
-        for (int q = 0; q < 5; ++q) zq[q][t] = 0.0;
-#pragma unroll
-        for (int q = 0; q < 3; ++q) mq[q][t] = 0.0;
+    for (int a = 0; a < NGY; ++a) {
+        const int rr = (tid + a * NT) / HX;
+        egy[a] = (tid + a * NT < TY * HX && j0 + rr < g.ny) ? g.eta_y[j0 + rr] : 0.0;
     }
 
-    auto load_plane = [&](double (*buf)[HP], int k) {
-        for (int p = tid; p < HP; p += NT) {
-            const int hx = p % HX, hy = p / HX;
-            const int gi = i0 - S + hx, gj = j0 - S + hy;
-            Prim q{1.0, 0.0, 0.0, 0.0, 1.0};
-            if (gi >= -g.ng && gi < g.nx + g.ng && gj >= -g.ng && gj < g.ny + g.ng)
-                q = load_prim(W, g.base + (long long)k * g.sz + (long long)gj * g.sy + gi, g.sv, gas);
-            buf[0][p] = q.r;
-            buf[1][p] = q.u;
-            buf[2][p] = q.v;
-            buf[3][p] = q.w;
-            buf[4][p] = q.T;
+    double m0[Q], m1[Q], m2[Q];   // D_x w, D_y w, D_x u + D_y v of this column
+#pragma unroll
+    for (int t = 0; t < Q; ++t) m0[t] = m1[t] = m2[t] = 0.0;
+
+    auto halo_index = [&](int q, int k) -> long long {
+        const int hx = q % HX, hy = q / HX;
+        const int gi = i0 - S + hx, gj = j0 - S + hy;
+        if (q < HP && gi >= -g.ng && gi < g.nx + g.ng && gj >= -g.ng && gj < g.ny + g.ng)
+            return g.base + (long long)k * g.sz + (long long)gj * g.sy + gi;
+        return -1;
+    };
+    auto fetch = [&](PlaneFetch<NPT>& f, int k, int nvar) {
+#pragma unroll
+        for (int a = 0; a < NPT; ++a) {
+            const long long n = halo_index(tid + a * NT, k);
+            f.q[a][0] = 1.0;
+            f.q[a][1] = f.q[a][2] = f.q[a][3] = 0.0;
+            f.q[a][4] = 1.0;
+            if (n >= 0) {
+#pragma unroll
+                for (int v = 0; v < 5; ++v)
+                    if (v < nvar) f.q[a][v] = W[n + v * g.sv];
+            }
         }
     };
-
-    // arrival: fill the last queue slot from sa (plane already staged)
+    auto fetch_col = [&](double (&cq)[5], int k) {
+        const long long n = col + (long long)k * g.sz;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) cq[v] = active ? W[n + v * g.sv] : (v == 0 ? 1.0 : 0.0);
+    };
+    double wc[5], rp[5];   // centre state and RK register of the next output node
+    auto fetch_centre = [&](int k) {
+        const long long n = col + (long long)k * g.sz;
+        const long long m = ((long long)k * g.ny + j) * g.nx + i;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) wc[v] = rp[v] = 0.0;
+        if (UPD && active) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) wc[v] = W[n + v * g.sv];
+            if (sc.read_prev) {
+#pragma unroll
+                for (int v = 0; v < 5; ++v) rp[v] = Rp[m + v * g.nint];
+            }
+        }
+    };
+    auto stage_arrival = [&](const PlaneFetch<NPT>& f) {
+#pragma unroll
+        for (int a = 0; a < NPT; ++a) {
+            const int q = tid + a * NT;
+            if (q < HP) {
+                const double ri = rcp(f.q[a][0]);
+                sa[0][q] = f.q[a][1] * ri;
+                sa[1][q] = f.q[a][2] * ri;
+                sa[2][q] = f.q[a][3] * ri;
+            }
+        }
+    };
+    auto stage_output = [&](const PlaneFetch<NPT>& f) {
+#pragma unroll
+        for (int a = 0; a < NPT; ++a) {
+            const int q = tid + a * NT;
+            if (q < HP) {
+                const double rho = f.q[a][0];
+                const double ri = rcp(rho);
+                const double u = f.q[a][1] * ri, v = f.q[a][2] * ri, w = f.q[a][3] * ri;
+                const double p = gas.gm1 * (f.q[a][4] - 0.5 * rho * (u * u + v * v + w * w));
+                const double T = gas.gM2 * p * ri;
+                double2* rec = reinterpret_cast<double2*>(so + 6 * q);
+                rec[0] = make_double2(rho, u);
+                rec[1] = make_double2(v, w);
+                rec[2] = make_double2(T, p);
+                sH[q] = (f.q[a][4] + p) * ri;
+            }
+        }
+    };
+    // column record of plane with ring slot `slot` from conserved values
+    auto stage_column = [&](int slot, const double (&cq)[5]) {
+        const double rho = cq[0];
+        const double ri = rcp(rho);
+        const double u = cq[1] * ri, v = cq[2] * ri, w = cq[3] * ri;
+        const double p = gas.gm1 * (cq[4] - 0.5 * rho * (u * u + v * v + w * w));
+        double2* rec = reinterpret_cast<double2*>(zring + 6 * (slot * NT + tid));
+        rec[0] = make_double2(rho, u);
+        rec[1] = make_double2(v, w);
+        rec[2] = make_double2(gas.gM2 * p * ri, (cq[4] + p) * ri);
+    };
+    auto znode = [&](int slot) -> Node {
+        const double2* rec = reinterpret_cast<const double2*>(zring + 6 * (slot * NT + tid));
+        const double2 a = rec[0], b = rec[1], e = rec[2];
+        return Node{a.x, a.y, b.x, b.y, e.x, a.x * e.x * gas.igM2, e.y};
+    };
+    // newest mixed-queue slot from the staged arrival plane
     auto arrive = [&]() {
         if (!active) return;
-#pragma unroll
-        for (int q = 0; q < 5; ++q) zq[q][Q - 1] = sa[q][c];
         double xw[Q], yw[Q], xu[Q], yv[Q];
 #pragma unroll
         for (int t = 0; t < Q; ++t) {
-            xw[t] = sa[3][c + t - S];
-            xu[t] = sa[1][c + t - S];
-            yw[t] = sa[3][c + (t - S) * HX];
-            yv[t] = sa[2][c + (t - S) * HX];
+            xu[t] = sa[0][c + t - S];
+            xw[t] = sa[2][c + t - S];
+            yv[t] = sa[1][c + (t - S) * HX];
+            yw[t] = sa[2][c + (t - S) * HX];
         }
-        mq[0][Q - 1] = dxi * d1<S>(xw);
-        mq[1][Q - 1] = ey * d1<S>(yw);
-        mq[2][Q - 1] = dxi * d1<S>(xu) + ey * d1<S>(yv);
+        m0[Q - 1] = dxi * d1<S>(xw);
+        m1[Q - 1] = ey * d1<S>(yw);
+        m2[Q - 1] = __builtin_fma(dxi, d1<S>(xu), ey * d1<S>(yv));
     };
-
     auto shift = [&]() {
 #pragma unroll
         for (int t = 0; t < Q - 1; ++t) {
-#pragma unroll
-            for (int q = 0; q < 5; ++q) zq[q][t] = zq[q][t + 1];
-#pragma unroll
-            for (int q = 0; q < 3; ++q) mq[q][t] = mq[q][t + 1];
+            m0[t] = m0[t + 1];
+            m1[t] = m1[t + 1];
+            m2[t] = m2[t + 1];
         }
     };
 
-    // prologue: planes k0-S .. k0+S-1 into queue slots 0 .. 2S-1
+    PlaneFetch<NPT> fa, fo;
+    double cq[5];
+
+    // prologue: planes k0-S .. k0+S-1 -> ring slots 0 .. 2S-1, mixed queue
     for (int t = 0; t < 2 * S; ++t) {
-        load_plane(sa, k0 - S + t);
+        fetch(fa, k0 - S + t, 4);
+        fetch_col(cq, k0 - S + t);
+        stage_arrival(fa);
+        stage_column(t, cq);
         __syncthreads();
         arrive();
         shift();
         __syncthreads();
     }
 
+    fetch(fa, k0 + S, 4);
+    fetch(fo, k0, 5);
+    fetch_col(cq, k0 + S);
+    fetch_centre(k0);
+
+    // results of the previous output plane, stored one iteration late
+    double pend[NV] = {0, 0, 0, 0, 0};
+    double pend_w[NV] = {0, 0, 0, 0, 0};
+    long long pend_n = -1, pend_m = -1;
+    auto flush = [&]() {
+        if (pend_n < 0) return;
+        if (UPD) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) out[v * g.sv + pend_n] = pend_w[v];
+            if (sc.write_prev) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) Rp[v * g.nint + pend_m] = pend[v];
+            }
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) out[v * g.nint + pend_m] = pend[v];
+        }
+        pend_n = -1;
+    };
+
+    int slot_k = S;   // ring slot of the output plane k (plane k0-S sits in slot 0)
     for (int k = k0; k < k1; ++k) {
-        load_plane(sa, k + S);
-        load_plane(so, k);
+        const int slot_new = slot_k + S >= Q ? slot_k + S - Q : slot_k + S;   // plane k+S
+        stage_arrival(fa);
+        stage_output(fo);
+        stage_column(slot_new, cq);
+        double wcur[5], rcur[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            wcur[v] = wc[v];
+            rcur[v] = rp[v];
+        }
+        flush();                       // stores of plane k-1
         __syncthreads();
         arrive();
+        if (k + 1 < k1) {              // loads of iteration k+1
+            fetch(fa, k + 1 + S, 4);
+            fetch(fo, k + 1, 5);
+            fetch_col(cq, k + 1 + S);
+            fetch_centre(k + 1);
+        }
+        sched_fence();
         // y-derivatives of u, v at plane k over the x-extended columns
-        for (int p = tid; p < TY * HX; p += NT) {
-            const int hx = p % HX, rr = p / HX;
-            const int jj = j0 + rr;
-            if (jj < g.ny) {
-                const double e = g.eta_y[jj];
+#pragma unroll
+        for (int a = 0; a < NGY; ++a) {
+            const int q = tid + a * NT;
+            const int hx = q % HX, rr = q / HX;
+            if (q < TY * HX && j0 + rr < g.ny) {
                 double su = 0.0, sv = 0.0;
 #pragma unroll
                 for (int l = 1; l <= S; ++l) {
-                    const int up = (rr + S + l) * HX + hx, dn = (rr + S - l) * HX + hx;
-                    su += Coef<S>::a[l] * (so[1][up] - so[1][dn]);
-                    sv += Coef<S>::a[l] * (so[2][up] - so[2][dn]);
+                    const int up = 6 * ((rr + S + l) * HX + hx), dn = 6 * ((rr + S - l) * HX + hx);
+                    su += Coef<S>::a[l] * (so[up + 1] - so[dn + 1]);
+                    sv += Coef<S>::a[l] * (so[up + 2] - so[dn + 2]);
                 }
-                gyl[0][rr][hx] = e * su;
-                gyl[1][rr][hx] = e * sv;
+                gyl[0][rr][hx] = egy[a] * su;
+                gyl[1][rr][hx] = egy[a] * sv;
             }
         }
         __syncthreads();
 
         if (active) {
             double acc[NV] = {0.0, 0.0, 0.0, 0.0, 0.0};
-            double xr[Q], xu[Q], xv[Q], xw[Q], xT[Q];
-            double yr[Q], yu[Q], yv[Q], yw[Q], yT[Q];
-#pragma unroll
-            for (int t = 0; t < Q; ++t) {
-                const int cx = c + t - S, cy = c + (t - S) * HX;
-                xr[t] = so[0][cx]; xu[t] = so[1][cx]; xv[t] = so[2][cx]; xw[t] = so[3][cx]; xT[t] = so[4][cx];
-                yr[t] = so[0][cy]; yu[t] = so[1][cy]; yv[t] = so[2][cy]; yw[t] = so[3][cy]; yT[t] = so[4][cy];
+            const bool visc = mask & SX_VISC;
+            const Node Cz = znode(slot_k);
+            const double uc = Cz.u, vc = Cz.v, wc_ = Cz.w, Tc = Cz.T;
+            double mu = 0.0, kcd = 0.0, smt = 0.0;
+            if (visc) {
+                mu = exp(gas.s * log(Tc)) * gas.ire;
+                kcd = mu * gas.cp * gas.ipr;
+                smt = gas.s * rcp(Tc);
             }
-            if (mask & SX_CONV_X) conv_dir<S, 0>(xr, xu, xv, xw, xT, gas, dxi, acc);
-            if (mask & SX_CONV_Y) conv_dir<S, 1>(yr, yu, yv, yw, yT, gas, ey, acc);
-            if (mask & SX_CONV_Z) conv_dir<S, 2>(zq[0], zq[1], zq[2], zq[3], zq[4], gas, dzi, acc);
-
-            if (mask & SX_VISC) {
-                const double uc = zq[1][S], vc = zq[2][S], wc = zq[3][S], Tc = zq[4][S];
-                // gradient tensor gab = d_b u_a and temperature gradient
-                const double g00 = dxi * d1<S>(xu), g01 = ey * d1<S>(yu), g02 = dzi * d1<S>(zq[1]);
-                const double g10 = dxi * d1<S>(xv), g11 = ey * d1<S>(yv), g12 = dzi * d1<S>(zq[2]);
-                const double g20 = dxi * d1<S>(xw), g21 = ey * d1<S>(yw), g22 = dzi * d1<S>(zq[3]);
-                const double Tx = dxi * d1<S>(xT), Ty = ey * d1<S>(yT), Tz = dzi * d1<S>(zq[4]);
-                const double dxi2 = dxi * dxi, dzi2 = dzi * dzi, ey2 = ey * ey;
-                const double uxx = dxi2 * d2<S>(xu), uyy = ey2 * d2<S>(yu) + eyy * d1<S>(yu), uzz = dzi2 * d2<S>(zq[1]);
-                const double vxx = dxi2 * d2<S>(xv), vyy = ey2 * d2<S>(yv) + eyy * d1<S>(yv), vzz = dzi2 * d2<S>(zq[2]);
-                const double wxx = dxi2 * d2<S>(xw), wyy = ey2 * d2<S>(yw) + eyy * d1<S>(yw), wzz = dzi2 * d2<S>(zq[3]);
-                const double Txx = dxi2 * d2<S>(xT), Tyy = ey2 * d2<S>(yT) + eyy * d1<S>(yT), Tzz = dzi2 * d2<S>(zq[4]);
-                // mixed derivatives
+            double gx[4] = {0, 0, 0, 0}, gy[4] = {0, 0, 0, 0}, gz[4] = {0, 0, 0, 0}, dd[4];
+            auto getx = [&](int t) { return node_from_record(so, sH, c + t); };
+            auto gety = [&](int t) { return node_from_record(so, sH, c + t * HX); };
+            auto getz = [&](int t) {
+                int sl = slot_k + t;
+                sl = sl < 0 ? sl + Q : (sl >= Q ? sl - Q : sl);
+                return znode(sl);
+            };
+            if (mask & SX_CONV_X) {
+                if (visc) stencil_dir<S, 0, true, true>(getx, dxi, dxi * dxi, 0.0, acc, gx, dd);
+                else stencil_dir<S, 0, true, false>(getx, dxi, dxi * dxi, 0.0, acc, gx, dd);
+            } else if (visc) {
+                stencil_dir<S, 0, false, true>(getx, dxi, dxi * dxi, 0.0, acc, gx, dd);
+            }
+            if (visc) visc_linear<0>(dd, mu, kcd, uc, vc, wc_, acc);
+            if (mask & SX_CONV_Y) {
+                if (visc) stencil_dir<S, 1, true, true>(gety, ey, ey * ey, eyy, acc, gy, dd);
+                else stencil_dir<S, 1, true, false>(gety, ey, ey * ey, eyy, acc, gy, dd);
+            } else if (visc) {
+                stencil_dir<S, 1, false, true>(gety, ey, ey * ey, eyy, acc, gy, dd);
+            }
+            if (visc) visc_linear<1>(dd, mu, kcd, uc, vc, wc_, acc);
+            if (mask & SX_CONV_Z) {
+                if (visc) stencil_dir<S, 2, true, true>(getz, dzi, dzi * dzi, 0.0, acc, gz, dd);
+                else stencil_dir<S, 2, true, false>(getz, dzi, dzi * dzi, 0.0, acc, gz, dd);
+            } else if (visc) {
+                stencil_dir<S, 2, false, true>(getz, dzi, dzi * dzi, 0.0, acc, gz, dd);
+            }
+            if (visc) {
+                visc_linear<2>(dd, mu, kcd, uc, vc, wc_, acc);
+                // mixed parts of mu/3 d_i(div u): d_x d_y, d_x d_z, d_y d_z
                 double gyu[Q], gyv[Q];
 #pragma unroll
                 for (int t = 0; t < Q; ++t) {
                     gyu[t] = gyl[0][ty][tx + t];
                     gyv[t] = gyl[1][ty][tx + t];
                 }
-                const double dxy_u = dxi * d1<S>(gyu);   // d_x d_y u
-                const double dxy_v = dxi * d1<S>(gyv);   // d_x d_y v
-                const double dxz_w = dzi * d1<S>(mq[0]); // d_z d_x w
-                const double dyz_w = dzi * d1<S>(mq[1]); // d_z d_y w
-                const double dz_div = dzi * d1<S>(mq[2]); // d_z (d_x u + d_y v)
+                const double m3 = mu * (1.0 / 3.0);
+                const double mx = m3 * (dxi * d1<S>(gyv) + dzi * d1<S>(m0));   // d_x d_y v + d_z d_x w
+                const double my = m3 * (dxi * d1<S>(gyu) + dzi * d1<S>(m1));   // d_x d_y u + d_z d_y w
+                const double mz = m3 * (dzi * d1<S>(m2));                      // d_z (d_x u + d_y v)
+                acc[1] += mx;
+                acc[2] += my;
+                acc[3] += mz;
+                acc[4] += uc * mx + vc * my + wc_ * mz;
+                // nonlinear parts: grad mu (= s mu/T grad T) terms and dissipation
+                const double g00 = gx[0], g10 = gx[1], g20 = gx[2], Tx = gx[3];
+                const double g01 = gy[0], g11 = gy[1], g21 = gy[2], Ty = gy[3];
+                const double g02 = gz[0], g12 = gz[1], g22 = gz[2], Tz = gz[3];
                 const double th = g00 + g11 + g22;
-                const double dth0 = uxx + dxy_v + dxz_w;
-                const double dth1 = vyy + dxy_u + dyz_w;
-                const double dth2 = wzz + dz_div;
-                const double mu = pow(Tc, gas.s) * gas.ire;
-                const double kc_ = mu * gas.cp * gas.ipr;
-                const double smt = gas.s / Tc;
-                const double dmu0 = smt * mu * Tx, dmu1 = smt * mu * Ty, dmu2 = smt * mu * Tz;
+                const double sm = smt * mu;
+                const double dmu0 = sm * Tx, dmu1 = sm * Ty, dmu2 = sm * Tz;
                 const double t3 = 2.0 / 3.0;
-                const double V0 = mu * ((uxx + uyy + uzz) + dth0 * (1.0 / 3.0)) + dmu0 * (g00 + g00) +
-                                  dmu1 * (g01 + g10) + dmu2 * (g02 + g20) - t3 * dmu0 * th;
-                const double V1 = mu * ((vxx + vyy + vzz) + dth1 * (1.0 / 3.0)) + dmu0 * (g10 + g01) +
-                                  dmu1 * (g11 + g11) + dmu2 * (g12 + g21) - t3 * dmu1 * th;
-                const double V2 = mu * ((wxx + wyy + wzz) + dth2 * (1.0 / 3.0)) + dmu0 * (g20 + g02) +
-                                  dmu1 * (g21 + g12) + dmu2 * (g22 + g22) - t3 * dmu2 * th;
-                // tau_ab d_b u_a
                 const double s01 = g01 + g10, s02 = g02 + g20, s12 = g12 + g21;
+                const double N0 = dmu0 * (2.0 * g00 - t3 * th) + dmu1 * s01 + dmu2 * s02;
+                const double N1 = dmu0 * s01 + dmu1 * (2.0 * g11 - t3 * th) + dmu2 * s12;
+                const double N2 = dmu0 * s02 + dmu1 * s12 + dmu2 * (2.0 * g22 - t3 * th);
                 const double diss = mu * ((2.0 * g00 - t3 * th) * g00 + (2.0 * g11 - t3 * th) * g11 +
                                           (2.0 * g22 - t3 * th) * g22 + s01 * s01 + s02 * s02 + s12 * s12);
-                const double dk = smt * kc_;
-                const double VE = uc * V0 + vc * V1 + wc * V2 + diss + kc_ * (Txx + Tyy + Tzz) +
-                                  dk * (Tx * Tx + Ty * Ty + Tz * Tz);
-                acc[1] += V0;
-                acc[2] += V1;
-                acc[3] += V2;
-                acc[4] += VE;
+                acc[1] += N0;
+                acc[2] += N1;
+                acc[3] += N2;
+                acc[4] += uc * N0 + vc * N1 + wc_ * N2 + diss + (smt * kcd) * (Tx * Tx + Ty * Ty + Tz * Tz);
             }
-
-            const long long m = ((long long)k * g.ny + j) * g.nx + i;
-            if (UPD) {
-                const long long n = g.base + (long long)k * g.sz + (long long)j * g.sy + i;
+            pend_m = ((long long)k * g.ny + j) * g.nx + i;
+            pend_n = col + (long long)k * g.sz;
 #pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    double nv = W[v * g.sv + n] + sc.cg * acc[v];
-                    if (sc.read_prev) nv += sc.cz * Rp[v * g.nint + m];
-                    out[v * g.sv + n] = nv;
-                    if (sc.write_prev) Rp[v * g.nint + m] = acc[v];
+            for (int v = 0; v < NV; ++v) {
+                pend[v] = acc[v];
+                if (UPD) {
+                    double nv = __builtin_fma(sc.cg, acc[v], wcur[v]);
+                    if (sc.read_prev) nv = __builtin_fma(sc.cz, rcur[v], nv);
+                    pend_w[v] = nv;
                 }
-            } else {
-#pragma unroll
-                for (int v = 0; v < NV; ++v) out[v * g.nint + m] = acc[v];
             }
         }
         shift();
+        slot_k = slot_k + 1 == Q ? 0 : slot_k + 1;
         __syncthreads();
     }
+    flush();
 }
 
 template <int S>
 static hipError_t launch_rhs_S(const KGrid& g, const KGas& gas, const double* W, double* out,
                                double* Rprev, const StepCoef* step, unsigned mask, hipStream_t st)
 {
-    constexpr int TX = 64, TY = 4;
+    constexpr int TX = 64, TY = S <= 3 ? 4 : 2;
     const int kc = g.nz;  // one march over the whole z extent per tile
     dim3 grid((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY, (g.nz + kc - 1) / kc);
     if (step) {
-        hipLaunchKernelGGL((k_rhs_central<S, TX, TY, true>), grid, dim3(TX * TY), 0, st, W, out, Rprev,
-                           g, gas, *step, (unsigned)SX_ALL, kc);
+        hipLaunchKernelGGL((k_rhs_central<S, TX, TY, true>), grid, dim3(TX * TY), 0, st, W, out,
+                           Rprev, g, gas, *step, (unsigned)SX_ALL, kc);
     } else {
         StepCoef none{0.0, 0.0, 0, 0};
         hipLaunchKernelGGL((k_rhs_central<S, TX, TY, false>), grid, dim3(TX * TY), 0, st, W, out,
