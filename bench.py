@@ -181,6 +181,30 @@ def main():
         "state_ok": ok,
         "wall_s_timed": wall,
     }
+    # the same workload in the FP32-flux precision form
+    h32 = sx.Handle(case, precision=sx.SX_FP32_FLUX)
+    W32 = h32.to_layout(Wn)
+    h32.sx_bind(W32)
+    for _ in range(args.warmup):
+        h32.sx_rk3_step(dt)
+    torch.cuda.synchronize()
+    h32.sx_timing_enable(True)
+    h32.sx_timing_read()
+    start.record()
+    for _ in range(args.steps):
+        h32.sx_rk3_step(dt)
+    stop.record()
+    torch.cuda.synchronize()
+    ms32 = start.elapsed_time(stop) / args.steps
+    n32, k32 = h32.sx_timing_read()
+    line["fp32_flux"] = {
+        "value": case.points / (ms32 * 1e-3),
+        "ms_per_step": ms32,
+        "speedup_vs_fp64": ms_per_step / ms32,
+        "launch_ms": k32 / n32,
+        "roofline_frac": ALG_BYTES_PER_POINT_STEP / SUBSTEPS * case.points / (k32 / n32 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+    }
+    del h32, W32
     if not args.no_cpu_baseline:
         del h, W0
         torch.cuda.empty_cache()

@@ -93,7 +93,9 @@ typedef struct {
     int central_order;        /* 2, 4, 6, 8 */
     int weno_order;           /* 1, 3, 5 */
     int visc_order;           /* must equal central_order in this build */
-    int sensor;               /* 0 off (pure central), 1 Ducros hybrid */
+    int sensor;               /* 0 off (pure central), 1 Ducros hybrid; the hybrid
+                                 allocates theta, face flags and a node list
+                                 (about 17 bytes per node) at sx_init */
     double sensor_thr;        /* WENO where max sensor over the stencil > thr */
     double sensor_eps;        /* epsilon of the sensor denominator */
     double weno_eps;          /* epsilon of the WENO weights */
@@ -177,6 +179,15 @@ int sx_compute_dt(sx_handle* h, double cfl, double* dt);
  * the stream. Returns SX_ENONFINITE when nonfinite or nonphysical > 0
  * (the struct is still filled). */
 int sx_diagnostics(sx_handle* h, const double* R, sx_diag* out);
+
+/* Face flags of the hybrid scheme supplied by the caller instead of the
+ * sensor (parity checks with injected flags; Section 2 hybrid switch).
+ * fx: uint8 [nz][ny][nx+1], fy: [nz][ny+1][nx], fz: [nz+1][ny][nx]; entry
+ * f of a line is the face between nodes f-1 and f; nonzero = WENO. Host or
+ * device pointers; the data is copied (synchronising). Passing three NULLs
+ * returns to the sensor. SX_ESTATE if the sensor is off. */
+int sx_set_flag_override(sx_handle* h, const unsigned char* fx, const unsigned char* fy,
+                         const unsigned char* fz);
 
 /* Kernel timing for measurement. When enabled, sx_rk3_step brackets every
  * launch of the fused right-hand-side/update kernel with HIP events recorded

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsx.so")
-SOURCES = ["sx_api.hip", "sx_ghost.hip", "sx_rhs.hip", "sx_reduce.hip"]
+SOURCES = ["sx_api.hip", "sx_ghost.hip", "sx_rhs.hip", "sx_reduce.hip", "sx_weno.hip"]
 ARCH = os.environ.get("SX_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

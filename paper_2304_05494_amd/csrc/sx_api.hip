@@ -19,6 +19,15 @@ struct sx_handle {
     sx::KScheme ks;
     double* d_metrics = nullptr;  // eta_y, eta_yy, y_eta  (3*ny)
     double* d_scratch = nullptr;  // reduction partials + results
+    // hybrid scheme (sensor on): theta, face flags, list of corrected nodes
+    double* d_theta = nullptr;
+    unsigned char* d_fx = nullptr;
+    unsigned char* d_fy = nullptr;
+    unsigned char* d_fz = nullptr;
+    int* d_list = nullptr;
+    int* d_count = nullptr;
+    unsigned long long* d_fcount = nullptr;
+    int flag_override = 0;
     double* W[2] = {nullptr, nullptr};
     double* Rprev = nullptr;
     hipStream_t st = nullptr;
@@ -125,8 +134,8 @@ int sx_init(const sx_grid* grid, const sx_gas* gas, const sx_scheme* scheme, sx_
     if (!valid_order(s.central_order) || !valid_order(s.visc_order)) return SX_EINVAL;
     if (s.weno_order != 1 && s.weno_order != 3 && s.weno_order != 5) return SX_EINVAL;
     if (s.visc_order != s.central_order) return SX_EUNSUPPORTED;
-    if (s.sensor != 0) return SX_EUNSUPPORTED;
-    if (s.precision != SX_FP64) return SX_EUNSUPPORTED;
+    if (s.sensor != 0 && s.sensor != 1) return SX_EINVAL;
+    if (s.precision != SX_FP64 && s.precision != SX_FP32_FLUX) return SX_EINVAL;
     if (!(gas->gamma > 1.0) || !(gas->mach > 0.0) || !(gas->reynolds > 0.0) || !(gas->prandtl > 0.0))
         return SX_EINVAL;
     if (!(g.lx > 0.0) || !(g.ly > 0.0) || !(g.lz > 0.0)) return SX_EINVAL;
@@ -188,6 +197,8 @@ int sx_init(const sx_grid* grid, const sx_gas* gas, const sx_scheme* scheme, sx_
     kgas.ire = 1.0 / gas->reynolds;
     kgas.ipr = 1.0 / gas->prandtl;
     kgas.t_wall = gas->t_wall;
+    kgas.pref = kgas.igM2;
+    kgas.href = kgas.cp;
 
     sx::KScheme& ks = h->ks;
     ks.L = L;
@@ -197,6 +208,7 @@ int sx_init(const sx_grid* grid, const sx_gas* gas, const sx_scheme* scheme, sx_
     ks.sensor_thr = s.sensor_thr;
     ks.sensor_eps = s.sensor_eps;
     ks.weno_eps = s.weno_eps;
+    ks.precision = s.precision;
 
     // metrics on the host, uploaded once
     const int ny = g.ny;
@@ -215,6 +227,16 @@ int sx_init(const sx_grid* grid, const sx_gas* gas, const sx_scheme* scheme, sx_
     delete[] hm;
     if (e == hipSuccess)
         e = hipMalloc(&h->d_scratch, sizeof(double) * (sx::kReduceBlocks + 1) * sx::kDiagVals);
+    if (e == hipSuccess && s.sensor) {
+        const long long ni = lay.interior;
+        e = hipMalloc(&h->d_theta, sizeof(double) * ni);
+        if (e == hipSuccess) e = hipMalloc(&h->d_fx, (size_t)g.nz * g.ny * (g.nx + 1));
+        if (e == hipSuccess) e = hipMalloc(&h->d_fy, (size_t)g.nz * (g.ny + 1) * g.nx);
+        if (e == hipSuccess) e = hipMalloc(&h->d_fz, (size_t)(g.nz + 1) * g.ny * g.nx);
+        if (e == hipSuccess) e = hipMalloc(&h->d_list, sizeof(int) * ni);
+        if (e == hipSuccess) e = hipMalloc(&h->d_count, sizeof(int));
+        if (e == hipSuccess) e = hipMalloc(&h->d_fcount, sizeof(unsigned long long) * 3);
+    }
     if (e != hipSuccess) {
         sx_finalize(h);
         return e == hipErrorOutOfMemory ? SX_ENOMEM : SX_EHIP;
@@ -231,6 +253,9 @@ void sx_finalize(sx_handle* h)
     if (!h) return;
     if (h->d_metrics) (void)hipFree(h->d_metrics);
     if (h->d_scratch) (void)hipFree(h->d_scratch);
+    for (void* p : {(void*)h->d_theta, (void*)h->d_fx, (void*)h->d_fy, (void*)h->d_fz,
+                    (void*)h->d_list, (void*)h->d_count, (void*)h->d_fcount})
+        if (p) (void)hipFree(p);
     for (auto* v : {&h->ev_used, &h->ev_free})
         for (auto& p : *v) {
             (void)hipEventDestroy(p.first);
@@ -289,6 +314,13 @@ int sx_rhs(sx_handle* h, double* W, double* R, unsigned term_mask)
     if (term_mask & ~(unsigned)SX_ALL) return fail(h, SX_EINVAL, "sx_rhs: unknown term bits");
     hipError_t e = sx::launch_ghost_fill(h->kg, h->kgas, W, h->st);
     if (e == hipSuccess) e = sx::launch_rhs(h->kg, h->kgas, h->ks, W, R, nullptr, nullptr, term_mask, h->st);
+    if (e == hipSuccess && h->ks.sensor && (term_mask & (SX_CONV_X | SX_CONV_Y | SX_CONV_Z))) {
+        e = sx::launch_sensor_flags(h->kg, h->ks, W, h->d_theta, h->d_fx, h->d_fy, h->d_fz,
+                                    h->flag_override, h->d_list, h->d_count, h->st);
+        if (e == hipSuccess)
+            e = sx::launch_weno(h->kg, h->kgas, h->ks, term_mask, W, h->d_fx, h->d_fy, h->d_fz,
+                                h->d_list, h->d_count, 0, 0.0, 0, R, nullptr, h->st);
+    }
     if (e != hipSuccess) return hip_fail(h, e, "sx_rhs");
     return SX_OK;
 }
@@ -310,6 +342,14 @@ int sx_rk3_step(sx_handle* h, double dt)
         if (e == hipSuccess)
             e = sx::launch_rhs(h->kg, h->kgas, h->ks, src, dst, h->Rprev, &sc, SX_ALL, h->st);
         if (e == hipSuccess && h->timing) e = timed_end(h, ev);
+        if (e == hipSuccess && h->ks.sensor) {
+            e = sx::launch_sensor_flags(h->kg, h->ks, src, h->d_theta, h->d_fx, h->d_fy, h->d_fz,
+                                        h->flag_override, h->d_list, h->d_count, h->st);
+            if (e == hipSuccess)
+                e = sx::launch_weno(h->kg, h->kgas, h->ks, SX_ALL, src, h->d_fx, h->d_fy, h->d_fz,
+                                    h->d_list, h->d_count, 1, sc.cg, sc.write_prev, dst, h->Rprev,
+                                    h->st);
+        }
         if (e != hipSuccess) return hip_fail(h, e, "sx_rk3_step");
         h->cur = 1 - h->cur;
     }
@@ -343,8 +383,25 @@ int sx_diagnostics(sx_handle* h, const double* R, sx_diag* out)
     if (e == hipSuccess)
         e = hipMemcpyAsync(v, h->d_scratch + (long long)nb * sx::kDiagVals, sizeof v,
                            hipMemcpyDeviceToHost, h->st);
+    unsigned long long fc[3] = {0, 0, 0};
+    if (e == hipSuccess && h->ks.sensor) {
+        double* Wc = h->W[h->cur];
+        e = sx::launch_ghost_fill(h->kg, h->kgas, Wc, h->st);
+        if (e == hipSuccess)
+            e = sx::launch_sensor_flags(h->kg, h->ks, Wc, h->d_theta, h->d_fx, h->d_fy, h->d_fz,
+                                        h->flag_override, h->d_list, h->d_count, h->st);
+        if (e == hipSuccess) e = sx::launch_count_flags(h->kg, h->d_fx, h->d_fy, h->d_fz, h->d_fcount, h->st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(fc, h->d_fcount, sizeof fc, hipMemcpyDeviceToHost, h->st);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(h->st);
     if (e != hipSuccess) return hip_fail(h, e, "sx_diagnostics");
+    if (h->ks.sensor) {
+        const sx_grid& g = h->grid;
+        v[12] = (double)fc[0] / ((double)g.nz * g.ny * (g.nx + 1));
+        v[13] = (double)fc[1] / ((double)g.nz * (g.ny + 1) * g.nx);
+        v[14] = (double)fc[2] / ((double)(g.nz + 1) * g.ny * g.nx);
+    }
     out->mass = v[0];
     out->momentum[0] = v[1];
     out->momentum[1] = v[2];
@@ -362,6 +419,28 @@ int sx_diagnostics(sx_handle* h, const double* R, sx_diag* out)
     out->weno_fraction[2] = v[14];
     out->volume = v[15];
     if (v[9] > 0.0 || v[10] > 0.0) return fail(h, SX_ENONFINITE, "sx_diagnostics: non-finite or non-physical state");
+    return SX_OK;
+}
+
+int sx_set_flag_override(sx_handle* h, const unsigned char* fx, const unsigned char* fy,
+                         const unsigned char* fz)
+{
+    if (!h) return SX_EINVAL;
+    if (!h->ks.sensor) return fail(h, SX_ESTATE, "sx_set_flag_override: sensor is off");
+    if (!fx && !fy && !fz) {
+        h->flag_override = 0;
+        return SX_OK;
+    }
+    if (!fx || !fy || !fz) return fail(h, SX_EINVAL, "sx_set_flag_override: need all three arrays");
+    const sx_grid& g = h->grid;
+    hipError_t e = hipMemcpyAsync(h->d_fx, fx, (size_t)g.nz * g.ny * (g.nx + 1), hipMemcpyDefault, h->st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->d_fy, fy, (size_t)g.nz * (g.ny + 1) * g.nx, hipMemcpyDefault, h->st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->d_fz, fz, (size_t)(g.nz + 1) * g.ny * g.nx, hipMemcpyDefault, h->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+    if (e != hipSuccess) return hip_fail(h, e, "sx_set_flag_override");
+    h->flag_override = 1;
     return SX_OK;
 }
 

@@ -33,6 +33,8 @@ struct KGas {
     double ire;                 // 1/Re
     double ipr;                 // 1/Pr
     double t_wall;
+    double pref;                // reference pressure 1/(gamma M^2) (FP32-flux shift)
+    double href;                // reference enthalpy c_p (FP32-flux shift)
 };
 
 struct KScheme {
@@ -41,6 +43,7 @@ struct KScheme {
     int r;                      // WENO half-width
     int sensor;
     double sensor_thr, sensor_eps, weno_eps;
+    int precision;              // SX_FP64 or SX_FP32_FLUX
 };
 
 // Central first-derivative weights a_l (D1 f = sum a_l (f_{+l} - f_{-l})) and
@@ -82,6 +85,15 @@ hipError_t launch_diagnostics(const KGrid& g, const KGas& gas, const KScheme& sc
                               int nscratch_blocks, hipStream_t st);
 hipError_t launch_max_rate(const KGrid& g, const KGas& gas, const double* W, double* scratch,
                            int nscratch_blocks, hipStream_t st);
+hipError_t launch_sensor_flags(const KGrid& g, const KScheme& sc, const double* W, double* theta,
+                               unsigned char* fx, unsigned char* fy, unsigned char* fz,
+                               int use_override, int* list, int* count, hipStream_t st);
+hipError_t launch_weno(const KGrid& g, const KGas& gas, const KScheme& sc, unsigned mask,
+                       const double* W, const unsigned char* fx, const unsigned char* fy,
+                       const unsigned char* fz, const int* list, const int* count, int mode,
+                       double cg, int write_prev, double* out, double* Rp, hipStream_t st);
+hipError_t launch_count_flags(const KGrid& g, const unsigned char* fx, const unsigned char* fy,
+                              const unsigned char* fz, unsigned long long* counts, hipStream_t st);
 
 constexpr int kReduceBlocks = 1024;   // partial-result slots of the reductions
 constexpr int kDiagVals = 16;

@@ -1,28 +1,38 @@
 // sx_rhs.hip -- fused right-hand side (+ low-storage RK3 update) for the
-// central split-form path: convective x/y/z derivatives, Laplacian-form
-// viscous and heat-flux terms (Section 2 of the paper), one kernel per
-// substep.
+// central split-form path: convective x/y/z derivatives and the
+// Laplacian-form viscous and heat-flux terms (Section 2 of the paper), one
+// kernel per substep.
 //
 // Mapping (gfx950, wave64): a workgroup owns a TX x TY column tile (lanes
-// along contiguous x, so every row load is coalesced) and marches along z
-// over a chunk of planes. Each iteration stages two planes in LDS with an
-// S-wide halo:
-//   * the arrival plane k+S (u, v, w) feeds per-column register queues of
-//     in-plane derivatives (D_x w, D_y w, D_x u + D_y v) whose z-derivatives
-//     are the mixed viscous terms; the column's own primitives at k+S enter
-//     a register queue that serves every z stencil;
-//   * the output plane k (rho, u, v, w, T, p as 48-byte records read with
-//     128-bit LDS loads, bank-conflict free) feeds the x and y stencils.
-// The y-derivatives of u and v are also computed over the x-halo columns
-// into a small LDS row so D_x(D_y .) costs one short stencil. Work at the
-// output node runs in x, y, z phases separated by scheduling barriers so
-// only one direction's stencil values are live at a time (two waves per
-// SIMD). The RHS of a node never leaves registers: in update mode the
-// kernel applies the RK3 substep and writes the new state and the RK
-// register, so HBM traffic per substep is one read of W, one write of W'
-// and the RK register.
+// along contiguous x, so every row load is coalesced) and marches along z.
+// Per plane step, LDS holds
+//   * the arrival plane k+S (u, v, w with an S-wide halo), whose in-plane
+//     derivatives D_x w, D_y w, D_x u + D_y v enter per-column register
+//     queues: their z-derivatives are the mixed viscous terms;
+//   * the output plane k (records rho, u, v, w, T, p, H with halo) for the
+//     x and y stencils, and D_y u, D_y v over the x-halo columns for the
+//     mixed x-y terms;
+//   * a ring of the last 2S+1 planes of every column's own primitives,
+//     which serves the z stencils.
+// Global loads of iteration k+1 are issued before the compute of iteration
+// k; the stores of iteration k are issued after the staging of k+1. The
+// RHS of a node never leaves registers: in update mode the kernel applies
+// the RK3 substep and writes the new state and the RK register, so the HBM
+// traffic of a substep is one read of W and Rprev, one write of W' and
+// Rprev.
+//
+// Precision forms: R = double (FP64 path) or R = float (FP32-flux form:
+// primitives are computed in FP64 and converted once per node, pressure
+// and enthalpy shifted by constant reference values first; all stencil and
+// flux arithmetic and the RHS accumulation run in FP32; the state, the RK
+// register and the update stay FP64). The shifts are exact corrections:
+// a constant pressure drops out of every difference, and a constant
+// enthalpy shift H' = H - H_ref changes the energy flux by H_ref times the
+// mass flux, added back in FP64 at the end.
 #include <stdlib.h>
 #include <string.h>
+
+#include <type_traits>
 
 #include "sx_internal.h"
 
@@ -40,77 +50,155 @@ __device__ __forceinline__ double rcp(double x)
 
 __device__ __forceinline__ void sched_fence() { __builtin_amdgcn_sched_barrier(0); }
 
-template <int S>
-__device__ __forceinline__ double d1(const double (&f)[2 * S + 1])
+template <int S, typename R>
+__device__ __forceinline__ R d1(const R (&f)[2 * S + 1])
 {
-    double s = 0.0;
+    R s = R(0);
 #pragma unroll
-    for (int l = 1; l <= S; ++l) s += Coef<S>::a[l] * (f[S + l] - f[S - l]);
+    for (int l = 1; l <= S; ++l) s += R(Coef<S>::a[l]) * (f[S + l] - f[S - l]);
     return s;
 }
 
-template <int S>
-__device__ __forceinline__ double d2(const double (&f)[2 * S + 1])
-{
-    double s = 0.0;
-#pragma unroll
-    for (int l = 1; l <= S; ++l) s += Coef<S>::b[l] * ((f[S + l] - 2.0 * f[S]) + f[S - l]);
-    return s;
-}
+template <typename R>
+__device__ __forceinline__ R powr(R x, R s);
+template <>
+__device__ __forceinline__ double powr<double>(double x, double s) { return exp(s * log(x)); }
+template <>
+__device__ __forceinline__ float powr<float>(float x, float s) { return expf(s * logf(x)); }
+
+template <typename R>
+__device__ __forceinline__ R rcpr(R x);
+template <>
+__device__ __forceinline__ double rcpr<double>(double x) { return rcp(x); }
+template <>
+__device__ __forceinline__ float rcpr<float>(float x) { return 1.0f / x; }
 
 // Node values along one stencil direction.
+template <typename R>
 struct Node {
-    double r, u, v, w, T, p, H;
+    R r, u, v, w, T, p, H;
 };
 
-__device__ __forceinline__ Node node_from_record(const double* __restrict__ so,
-                                                 const double* __restrict__ sH, int q)
+// LDS record layouts. FP64: plane records of 6 doubles (read as three
+// 128-bit loads; the 48-byte stride is bank-conflict free) plus a separate
+// enthalpy array; ring records (rho,u,v,w,T,H) with p derived. FP32: 7-float
+// records (rho,u,v,w,T,p',H') read as 32-bit loads (stride 7 is coprime
+// with the 64 banks).
+template <typename R>
+struct Layout;
+template <>
+struct Layout<double> {
+    static constexpr int PREC = 6;   // plane record
+    static constexpr int ZREC = 6;   // ring record
+    static constexpr bool SEP_H = true;
+};
+template <>
+struct Layout<float> {
+    static constexpr int PREC = 7;
+    static constexpr int ZREC = 7;
+    static constexpr bool SEP_H = false;
+};
+
+template <typename R>
+__device__ __forceinline__ void plane_write(R* so, R* sH, int q, double rho, double u, double v,
+                                            double w, double T, double p, double H)
 {
-    const double2* rec = reinterpret_cast<const double2*>(so + 6 * q);
-    const double2 a = rec[0], b = rec[1], e = rec[2];
-    return Node{a.x, a.y, b.x, b.y, e.x, e.y, sH[q]};
+    if constexpr (std::is_same<R, double>::value) {
+        double2* rec = reinterpret_cast<double2*>(so + 6 * q);
+        rec[0] = make_double2(rho, u);
+        rec[1] = make_double2(v, w);
+        rec[2] = make_double2(T, p);
+        sH[q] = H;
+    } else {
+        R* rec = so + 7 * q;
+        rec[0] = R(rho); rec[1] = R(u); rec[2] = R(v); rec[3] = R(w);
+        rec[4] = R(T); rec[5] = R(p); rec[6] = R(H);
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ Node<R> plane_read(const R* so, const R* sH, int q)
+{
+    if constexpr (std::is_same<R, double>::value) {
+        const double2* rec = reinterpret_cast<const double2*>(so + 6 * q);
+        const double2 a = rec[0], b = rec[1], e = rec[2];
+        return Node<double>{a.x, a.y, b.x, b.y, e.x, e.y, sH[q]};
+    } else {
+        const R* rec = so + 7 * q;
+        return Node<R>{rec[0], rec[1], rec[2], rec[3], rec[4], rec[5], rec[6]};
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void ring_write(R* z, double rho, double u, double v, double w,
+                                           double T, double p, double H)
+{
+    if constexpr (std::is_same<R, double>::value) {
+        double2* rec = reinterpret_cast<double2*>(z);
+        rec[0] = make_double2(rho, u);
+        rec[1] = make_double2(v, w);
+        rec[2] = make_double2(T, H);
+        (void)p;
+    } else {
+        z[0] = R(rho); z[1] = R(u); z[2] = R(v); z[3] = R(w); z[4] = R(T); z[5] = R(p); z[6] = R(H);
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ Node<R> ring_read(const R* z, R igM2)
+{
+    if constexpr (std::is_same<R, double>::value) {
+        const double2* rec = reinterpret_cast<const double2*>(z);
+        const double2 a = rec[0], b = rec[1], e = rec[2];
+        return Node<double>{a.x, a.y, b.x, b.y, e.x, a.x * e.x * igM2, e.y};
+    } else {
+        return Node<R>{z[0], z[1], z[2], z[3], z[4], z[5], z[6]};
+    }
 }
 
 // One direction of the output node, streaming the stencil pairs l = 1..S
-// so only the centre and the two nodes at distance l are live: adds the
-// split-form convective derivative (pair-difference form, see conv_dir)
+// so only the centre and the two nodes at distance l are live. Adds the
+// convective derivative in the pair-difference form of the split flux,
+//   F_{i+1/2} - F_{i-1/2} = sum_l 2 a_l [P_l(i) - P_l(i-l)],
+//   P_l(n) = 1/8 (rho_n + rho_{n+l})(ud_n + ud_{n+l})(phi_n + phi_{n+l}),
+// phi in {1, u, v, w, H}, pressure 1/2 (p_n + p_{n+l}) in the D-momentum,
 // to acc and returns first derivatives gd = (u, v, w, T)_n and the pure
 // second derivatives dd = (u, v, w, T)_nn (sc: metric 1/h or eta_y;
 // sc2 = sc^2; scy = eta_yy along y, 0 otherwise).
-template <int S, int D, bool CONV, bool VISC, typename Get>
-__device__ __forceinline__ void stencil_dir(Get get, double sc, double sc2, double scy,
-                                            double (&acc)[NV], double (&gd)[4], double (&dd)[4])
+template <int S, int D, bool CONV, bool VISC, typename R, typename Get>
+__device__ __forceinline__ void stencil_dir(Get get, R sc, R sc2, R scy, R (&acc)[NV], R (&gd)[4],
+                                            R (&dd)[4])
 {
-    const Node C = get(0);
-    double f0 = 0.0, f1 = 0.0, f2 = 0.0, f3 = 0.0, f4 = 0.0, fp = 0.0;
-    double s1[4] = {0.0, 0.0, 0.0, 0.0}, s2[4] = {0.0, 0.0, 0.0, 0.0};
+    const Node<R> C = get(0);
+    R f0 = 0, f1 = 0, f2 = 0, f3 = 0, f4 = 0, fp = 0;
+    R s1[4] = {0, 0, 0, 0}, s2[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int l = 1; l <= S; ++l) {
-        const Node M = get(-l), P = get(l);
+        const Node<R> M = get(-l), P = get(l);
         if (CONV) {
-            const double cl = 0.25 * Coef<S>::a[l];
-            const double udC = D == 0 ? C.u : (D == 1 ? C.v : C.w);
-            const double udP = D == 0 ? P.u : (D == 1 ? P.v : P.w);
-            const double udM = D == 0 ? M.u : (D == 1 ? M.v : M.w);
-            const double mp = cl * (C.r + P.r) * (udC + udP);    // pair (C, P), +
-            const double mm = cl * (M.r + C.r) * (udM + udC);    // pair (M, C), -
-            f0 += 2.0 * (mp - mm);
+            const R cl = R(0.25 * Coef<S>::a[l]);
+            const R udC = D == 0 ? C.u : (D == 1 ? C.v : C.w);
+            const R udP = D == 0 ? P.u : (D == 1 ? P.v : P.w);
+            const R udM = D == 0 ? M.u : (D == 1 ? M.v : M.w);
+            const R mp = cl * (C.r + P.r) * (udC + udP);    // pair (C, P), +
+            const R mm = cl * (M.r + C.r) * (udM + udC);    // pair (M, C), -
+            f0 += R(2) * (mp - mm);
             f1 += mp * (C.u + P.u) - mm * (M.u + C.u);
             f2 += mp * (C.v + P.v) - mm * (M.v + C.v);
             f3 += mp * (C.w + P.w) - mm * (M.w + C.w);
             f4 += mp * (C.H + P.H) - mm * (M.H + C.H);
-            fp += (4.0 * cl) * (P.p - M.p);
+            fp += (R(4) * cl) * (P.p - M.p);
         }
         if (VISC) {
-            const double al = Coef<S>::a[l], bl = Coef<S>::b[l];
+            const R al = R(Coef<S>::a[l]), bl = R(Coef<S>::b[l]);
             s1[0] += al * (P.u - M.u);
             s1[1] += al * (P.v - M.v);
             s1[2] += al * (P.w - M.w);
             s1[3] += al * (P.T - M.T);
-            s2[0] += bl * ((P.u - 2.0 * C.u) + M.u);
-            s2[1] += bl * ((P.v - 2.0 * C.v) + M.v);
-            s2[2] += bl * ((P.w - 2.0 * C.w) + M.w);
-            s2[3] += bl * ((P.T - 2.0 * C.T) + M.T);
+            s2[0] += bl * ((P.u - R(2) * C.u) + M.u);
+            s2[1] += bl * ((P.v - R(2) * C.v) + M.v);
+            s2[2] += bl * ((P.w - R(2) * C.w) + M.w);
+            s2[3] += bl * ((P.T - R(2) * C.T) + M.T);
         }
     }
     if (CONV) {
@@ -127,7 +215,7 @@ __device__ __forceinline__ void stencil_dir(Get get, double sc, double sc2, doub
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             gd[q] = sc * s1[q];
-            dd[q] = __builtin_fma(sc2, s2[q], scy * s1[q]);
+            dd[q] = sc2 * s2[q] + scy * s1[q];
         }
     }
 }
@@ -135,12 +223,12 @@ __device__ __forceinline__ void stencil_dir(Get get, double sc, double sc2, doub
 // Linear viscous pieces of one direction d, consumed at once:
 // mu (u_i)_dd (+ mu/3 (u_d)_dd into momentum d), k T_dd, and their work
 // u_i (...) into the energy.
-template <int D>
-__device__ __forceinline__ void visc_linear(const double (&dd)[4], double mu, double kc, double uc,
-                                            double vc, double wc, double (&acc)[NV])
+template <int D, typename R>
+__device__ __forceinline__ void visc_linear(const R (&dd)[4], R mu, R kc, R uc, R vc, R wc,
+                                            R (&acc)[NV])
 {
-    const double o3 = 1.0 / 3.0;
-    double a0 = mu * dd[0], a1 = mu * dd[1], a2 = mu * dd[2];
+    const R o3 = R(1.0 / 3.0);
+    R a0 = mu * dd[0], a1 = mu * dd[1], a2 = mu * dd[2];
     if (D == 0) a0 += (mu * o3) * dd[0];
     if (D == 1) a1 += (mu * o3) * dd[1];
     if (D == 2) a2 += (mu * o3) * dd[2];
@@ -157,30 +245,24 @@ struct PlaneFetch {
     double q[NPT][5];
 };
 
-// One workgroup (TX x TY columns, one wave per SIMD) marches a column tile
-// along z. LDS holds: the arrival plane k+S (u, v, w with halo), the output
-// plane k (records rho,u,v,w,T,p + enthalpy, with halo), D_y u and D_y v
-// over the x-halo columns, and a ring of the last 2S+1 planes of every
-// column's own primitives (rho,u,v,w,T,H) that serves the z stencils. The
-// in-plane derivatives whose z-derivatives are the mixed viscous terms stay
-// in register queues. Global loads of iteration k+1 are issued before the
-// compute of iteration k, and the stores of iteration k are issued after the
-// staging of iteration k+1, so neither waits on the other.
-template <int S, int TX, int TY, bool UPD>
-__global__ void __attribute__((amdgpu_flat_work_group_size(TX * TY, TX * TY), amdgpu_waves_per_eu(1)))
+template <int S, int TX, int TY, int WPE, typename R, bool UPD>
+__global__ void __attribute__((amdgpu_flat_work_group_size(TX * TY, TX * TY), amdgpu_waves_per_eu(WPE)))
 k_rhs_central(const double* __restrict__ W, double* __restrict__ out, double* __restrict__ Rp,
               KGrid g, KGas gas, StepCoef sc, unsigned mask, int kc)
 {
+    using L = Layout<R>;
     constexpr int NT = TX * TY;
     constexpr int HX = TX + 2 * S, HY = TY + 2 * S, HP = HX * HY;
     constexpr int NPT = (HP + NT - 1) / NT;
     constexpr int Q = 2 * S + 1;
-    __shared__ double sa[3][HP];                                  // arrival plane: u, v, w
-    __shared__ __attribute__((aligned(16))) double so[6 * HP];    // output plane records
-    __shared__ double sH[HP];                                     // output plane enthalpy
-    __shared__ double gyl[2][TY][HX];                             // D_y u, D_y v of plane k
-    __shared__ __attribute__((aligned(16))) double zring[Q * NT * 6];  // column records
+    __shared__ R sa[3][HP];                                        // arrival plane: u, v, w
+    __shared__ __attribute__((aligned(16))) R so[L::PREC * HP];    // output plane records
+    __shared__ R sH[L::SEP_H ? HP : 1];                            // output plane enthalpy
+    __shared__ R gyl[2][TY][HX];                                   // D_y u, D_y v of plane k
+    __shared__ __attribute__((aligned(16))) R zring[Q * NT * L::ZREC];  // column records
 
+    constexpr bool f32 = std::is_same<R, float>::value;
+    const double pref = f32 ? gas.pref : 0.0, href = f32 ? gas.href : 0.0;
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
     const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
@@ -189,21 +271,22 @@ k_rhs_central(const double* __restrict__ W, double* __restrict__ out, double* __
     const int i = i0 + tx, j = j0 + ty;
     const bool active = i < g.nx && j < g.ny;
     const int c = (ty + S) * HX + (tx + S);
-    const double ey = active ? g.eta_y[j] : 0.0;
-    const double eyy = active ? g.eta_yy[j] : 0.0;
-    const double dxi = g.dxi, dzi = g.dzi;
+    const R ey = active ? R(g.eta_y[j]) : R(0);
+    const R eyy = active ? R(g.eta_yy[j]) : R(0);
+    const R dxi = R(g.dxi), dzi = R(g.dzi);
+    const R igM2 = R(gas.igM2);
     const long long col = g.base + (long long)j * g.sy + i;   // this column at k = 0
     constexpr int NGY = (TY * HX + NT - 1) / NT;
-    double egy[NGY];                                          // eta_y of the D_y rows
+    R egy[NGY];                                               // eta_y of the D_y rows
 #pragma unroll
     for (int a = 0; a < NGY; ++a) {
         const int rr = (tid + a * NT) / HX;
-        egy[a] = (tid + a * NT < TY * HX && j0 + rr < g.ny) ? g.eta_y[j0 + rr] : 0.0;
+        egy[a] = (tid + a * NT < TY * HX && j0 + rr < g.ny) ? R(g.eta_y[j0 + rr]) : R(0);
     }
 
-    double m0[Q], m1[Q], m2[Q];   // D_x w, D_y w, D_x u + D_y v of this column
+    R m0[Q], m1[Q], m2[Q];   // D_x w, D_y w, D_x u + D_y v of this column
 #pragma unroll
-    for (int t = 0; t < Q; ++t) m0[t] = m1[t] = m2[t] = 0.0;
+    for (int t = 0; t < Q; ++t) m0[t] = m1[t] = m2[t] = R(0);
 
     auto halo_index = [&](int q, int k) -> long long {
         const int hx = q % HX, hy = q / HX;
@@ -252,50 +335,47 @@ k_rhs_central(const double* __restrict__ W, double* __restrict__ out, double* __
             const int q = tid + a * NT;
             if (q < HP) {
                 const double ri = rcp(f.q[a][0]);
-                sa[0][q] = f.q[a][1] * ri;
-                sa[1][q] = f.q[a][2] * ri;
-                sa[2][q] = f.q[a][3] * ri;
+                sa[0][q] = R(f.q[a][1] * ri);
+                sa[1][q] = R(f.q[a][2] * ri);
+                sa[2][q] = R(f.q[a][3] * ri);
             }
         }
+    };
+    // FP64 primitives of conserved values (pressure / enthalpy shifted by
+    // the reference values in the FP32 form)
+    auto prims = [&](const double* w5, double& rho, double& u, double& v, double& w, double& T,
+                     double& p, double& H) {
+        rho = w5[0];
+        const double ri = rcp(rho);
+        u = w5[1] * ri;
+        v = w5[2] * ri;
+        w = w5[3] * ri;
+        const double pr = gas.gm1 * (w5[4] - 0.5 * rho * (u * u + v * v + w * w));
+        T = gas.gM2 * pr * ri;
+        H = (w5[4] + pr) * ri - href;
+        p = pr - pref;
     };
     auto stage_output = [&](const PlaneFetch<NPT>& f) {
 #pragma unroll
         for (int a = 0; a < NPT; ++a) {
             const int q = tid + a * NT;
             if (q < HP) {
-                const double rho = f.q[a][0];
-                const double ri = rcp(rho);
-                const double u = f.q[a][1] * ri, v = f.q[a][2] * ri, w = f.q[a][3] * ri;
-                const double p = gas.gm1 * (f.q[a][4] - 0.5 * rho * (u * u + v * v + w * w));
-                const double T = gas.gM2 * p * ri;
-                double2* rec = reinterpret_cast<double2*>(so + 6 * q);
-                rec[0] = make_double2(rho, u);
-                rec[1] = make_double2(v, w);
-                rec[2] = make_double2(T, p);
-                sH[q] = (f.q[a][4] + p) * ri;
+                double rho, u, v, w, T, p, H;
+                prims(f.q[a], rho, u, v, w, T, p, H);
+                plane_write<R>(so, sH, q, rho, u, v, w, T, p, H);
             }
         }
     };
-    // column record of plane with ring slot `slot` from conserved values
     auto stage_column = [&](int slot, const double (&cq)[5]) {
-        const double rho = cq[0];
-        const double ri = rcp(rho);
-        const double u = cq[1] * ri, v = cq[2] * ri, w = cq[3] * ri;
-        const double p = gas.gm1 * (cq[4] - 0.5 * rho * (u * u + v * v + w * w));
-        double2* rec = reinterpret_cast<double2*>(zring + 6 * (slot * NT + tid));
-        rec[0] = make_double2(rho, u);
-        rec[1] = make_double2(v, w);
-        rec[2] = make_double2(gas.gM2 * p * ri, (cq[4] + p) * ri);
+        double rho, u, v, w, T, p, H;
+        prims(cq, rho, u, v, w, T, p, H);
+        ring_write<R>(zring + L::ZREC * (slot * NT + tid), rho, u, v, w, T, p, H);
     };
-    auto znode = [&](int slot) -> Node {
-        const double2* rec = reinterpret_cast<const double2*>(zring + 6 * (slot * NT + tid));
-        const double2 a = rec[0], b = rec[1], e = rec[2];
-        return Node{a.x, a.y, b.x, b.y, e.x, a.x * e.x * gas.igM2, e.y};
-    };
+    auto znode = [&](int slot) { return ring_read<R>(zring + L::ZREC * (slot * NT + tid), igM2); };
     // newest mixed-queue slot from the staged arrival plane
     auto arrive = [&]() {
         if (!active) return;
-        double xw[Q], yw[Q], xu[Q], yv[Q];
+        R xw[Q], yw[Q], xu[Q], yv[Q];
 #pragma unroll
         for (int t = 0; t < Q; ++t) {
             xu[t] = sa[0][c + t - S];
@@ -305,7 +385,7 @@ k_rhs_central(const double* __restrict__ W, double* __restrict__ out, double* __
         }
         m0[Q - 1] = dxi * d1<S>(xw);
         m1[Q - 1] = ey * d1<S>(yw);
-        m2[Q - 1] = __builtin_fma(dxi, d1<S>(xu), ey * d1<S>(yv));
+        m2[Q - 1] = dxi * d1<S>(xu) + ey * d1<S>(yv);
     };
     auto shift = [&]() {
 #pragma unroll
@@ -384,12 +464,12 @@ k_rhs_central(const double* __restrict__ W, double* __restrict__ out, double* __
             const int q = tid + a * NT;
             const int hx = q % HX, rr = q / HX;
             if (q < TY * HX && j0 + rr < g.ny) {
-                double su = 0.0, sv = 0.0;
+                R su = 0, sv = 0;
 #pragma unroll
                 for (int l = 1; l <= S; ++l) {
-                    const int up = 6 * ((rr + S + l) * HX + hx), dn = 6 * ((rr + S - l) * HX + hx);
-                    su += Coef<S>::a[l] * (so[up + 1] - so[dn + 1]);
-                    sv += Coef<S>::a[l] * (so[up + 2] - so[dn + 2]);
+                    const int up = L::PREC * ((rr + S + l) * HX + hx), dn = L::PREC * ((rr + S - l) * HX + hx);
+                    su += R(Coef<S>::a[l]) * (so[up + 1] - so[dn + 1]);
+                    sv += R(Coef<S>::a[l]) * (so[up + 2] - so[dn + 2]);
                 }
                 gyl[0][rr][hx] = egy[a] * su;
                 gyl[1][rr][hx] = egy[a] * sv;
@@ -398,29 +478,29 @@ k_rhs_central(const double* __restrict__ W, double* __restrict__ out, double* __
         __syncthreads();
 
         if (active) {
-            double acc[NV] = {0.0, 0.0, 0.0, 0.0, 0.0};
+            R acc[NV] = {0, 0, 0, 0, 0};
             const bool visc = mask & SX_VISC;
-            const Node Cz = znode(slot_k);
-            const double uc = Cz.u, vc = Cz.v, wc_ = Cz.w, Tc = Cz.T;
-            double mu = 0.0, kcd = 0.0, smt = 0.0;
+            const Node<R> Cz = znode(slot_k);
+            const R uc = Cz.u, vc = Cz.v, wc_ = Cz.w, Tc = Cz.T;
+            R mu = 0, kcd = 0, smt = 0;
             if (visc) {
-                mu = exp(gas.s * log(Tc)) * gas.ire;
-                kcd = mu * gas.cp * gas.ipr;
-                smt = gas.s * rcp(Tc);
+                mu = powr<R>(Tc, R(gas.s)) * R(gas.ire);
+                kcd = mu * R(gas.cp * gas.ipr);
+                smt = R(gas.s) * rcpr<R>(Tc);
             }
-            double gx[4] = {0, 0, 0, 0}, gy[4] = {0, 0, 0, 0}, gz[4] = {0, 0, 0, 0}, dd[4];
-            auto getx = [&](int t) { return node_from_record(so, sH, c + t); };
-            auto gety = [&](int t) { return node_from_record(so, sH, c + t * HX); };
+            R gx[4] = {0, 0, 0, 0}, gy[4] = {0, 0, 0, 0}, gz[4] = {0, 0, 0, 0}, dd[4];
+            auto getx = [&](int t) { return plane_read<R>(so, sH, c + t); };
+            auto gety = [&](int t) { return plane_read<R>(so, sH, c + t * HX); };
             auto getz = [&](int t) {
                 int sl = slot_k + t;
                 sl = sl < 0 ? sl + Q : (sl >= Q ? sl - Q : sl);
                 return znode(sl);
             };
             if (mask & SX_CONV_X) {
-                if (visc) stencil_dir<S, 0, true, true>(getx, dxi, dxi * dxi, 0.0, acc, gx, dd);
-                else stencil_dir<S, 0, true, false>(getx, dxi, dxi * dxi, 0.0, acc, gx, dd);
+                if (visc) stencil_dir<S, 0, true, true>(getx, dxi, dxi * dxi, R(0), acc, gx, dd);
+                else stencil_dir<S, 0, true, false>(getx, dxi, dxi * dxi, R(0), acc, gx, dd);
             } else if (visc) {
-                stencil_dir<S, 0, false, true>(getx, dxi, dxi * dxi, 0.0, acc, gx, dd);
+                stencil_dir<S, 0, false, true>(getx, dxi, dxi * dxi, R(0), acc, gx, dd);
             }
             if (visc) visc_linear<0>(dd, mu, kcd, uc, vc, wc_, acc);
             if (mask & SX_CONV_Y) {
@@ -431,42 +511,44 @@ k_rhs_central(const double* __restrict__ W, double* __restrict__ out, double* __
             }
             if (visc) visc_linear<1>(dd, mu, kcd, uc, vc, wc_, acc);
             if (mask & SX_CONV_Z) {
-                if (visc) stencil_dir<S, 2, true, true>(getz, dzi, dzi * dzi, 0.0, acc, gz, dd);
-                else stencil_dir<S, 2, true, false>(getz, dzi, dzi * dzi, 0.0, acc, gz, dd);
+                if (visc) stencil_dir<S, 2, true, true>(getz, dzi, dzi * dzi, R(0), acc, gz, dd);
+                else stencil_dir<S, 2, true, false>(getz, dzi, dzi * dzi, R(0), acc, gz, dd);
             } else if (visc) {
-                stencil_dir<S, 2, false, true>(getz, dzi, dzi * dzi, 0.0, acc, gz, dd);
+                stencil_dir<S, 2, false, true>(getz, dzi, dzi * dzi, R(0), acc, gz, dd);
             }
+            // enthalpy shift correction of the convective energy flux (FP64)
+            const double accE_shift = href * double(acc[0]);
             if (visc) {
                 visc_linear<2>(dd, mu, kcd, uc, vc, wc_, acc);
                 // mixed parts of mu/3 d_i(div u): d_x d_y, d_x d_z, d_y d_z
-                double gyu[Q], gyv[Q];
+                R gyu[Q], gyv[Q];
 #pragma unroll
                 for (int t = 0; t < Q; ++t) {
                     gyu[t] = gyl[0][ty][tx + t];
                     gyv[t] = gyl[1][ty][tx + t];
                 }
-                const double m3 = mu * (1.0 / 3.0);
-                const double mx = m3 * (dxi * d1<S>(gyv) + dzi * d1<S>(m0));   // d_x d_y v + d_z d_x w
-                const double my = m3 * (dxi * d1<S>(gyu) + dzi * d1<S>(m1));   // d_x d_y u + d_z d_y w
-                const double mz = m3 * (dzi * d1<S>(m2));                      // d_z (d_x u + d_y v)
+                const R m3 = mu * R(1.0 / 3.0);
+                const R mx = m3 * (dxi * d1<S>(gyv) + dzi * d1<S>(m0));   // d_x d_y v + d_z d_x w
+                const R my = m3 * (dxi * d1<S>(gyu) + dzi * d1<S>(m1));   // d_x d_y u + d_z d_y w
+                const R mz = m3 * (dzi * d1<S>(m2));                      // d_z (d_x u + d_y v)
                 acc[1] += mx;
                 acc[2] += my;
                 acc[3] += mz;
                 acc[4] += uc * mx + vc * my + wc_ * mz;
                 // nonlinear parts: grad mu (= s mu/T grad T) terms and dissipation
-                const double g00 = gx[0], g10 = gx[1], g20 = gx[2], Tx = gx[3];
-                const double g01 = gy[0], g11 = gy[1], g21 = gy[2], Ty = gy[3];
-                const double g02 = gz[0], g12 = gz[1], g22 = gz[2], Tz = gz[3];
-                const double th = g00 + g11 + g22;
-                const double sm = smt * mu;
-                const double dmu0 = sm * Tx, dmu1 = sm * Ty, dmu2 = sm * Tz;
-                const double t3 = 2.0 / 3.0;
-                const double s01 = g01 + g10, s02 = g02 + g20, s12 = g12 + g21;
-                const double N0 = dmu0 * (2.0 * g00 - t3 * th) + dmu1 * s01 + dmu2 * s02;
-                const double N1 = dmu0 * s01 + dmu1 * (2.0 * g11 - t3 * th) + dmu2 * s12;
-                const double N2 = dmu0 * s02 + dmu1 * s12 + dmu2 * (2.0 * g22 - t3 * th);
-                const double diss = mu * ((2.0 * g00 - t3 * th) * g00 + (2.0 * g11 - t3 * th) * g11 +
-                                          (2.0 * g22 - t3 * th) * g22 + s01 * s01 + s02 * s02 + s12 * s12);
+                const R g00 = gx[0], g10 = gx[1], g20 = gx[2], Tx = gx[3];
+                const R g01 = gy[0], g11 = gy[1], g21 = gy[2], Ty = gy[3];
+                const R g02 = gz[0], g12 = gz[1], g22 = gz[2], Tz = gz[3];
+                const R th = g00 + g11 + g22;
+                const R sm = smt * mu;
+                const R dmu0 = sm * Tx, dmu1 = sm * Ty, dmu2 = sm * Tz;
+                const R t3 = R(2.0 / 3.0);
+                const R s01 = g01 + g10, s02 = g02 + g20, s12 = g12 + g21;
+                const R N0 = dmu0 * (R(2) * g00 - t3 * th) + dmu1 * s01 + dmu2 * s02;
+                const R N1 = dmu0 * s01 + dmu1 * (R(2) * g11 - t3 * th) + dmu2 * s12;
+                const R N2 = dmu0 * s02 + dmu1 * s12 + dmu2 * (R(2) * g22 - t3 * th);
+                const R diss = mu * ((R(2) * g00 - t3 * th) * g00 + (R(2) * g11 - t3 * th) * g11 +
+                                     (R(2) * g22 - t3 * th) * g22 + s01 * s01 + s02 * s02 + s12 * s12);
                 acc[1] += N0;
                 acc[2] += N1;
                 acc[3] += N2;
@@ -476,9 +558,11 @@ k_rhs_central(const double* __restrict__ W, double* __restrict__ out, double* __
             pend_n = col + (long long)k * g.sz;
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                pend[v] = acc[v];
+                double r = double(acc[v]);
+                if (f32 && v == 4) r += accE_shift;
+                pend[v] = r;
                 if (UPD) {
-                    double nv = __builtin_fma(sc.cg, acc[v], wcur[v]);
+                    double nv = __builtin_fma(sc.cg, r, wcur[v]);
                     if (sc.read_prev) nv = __builtin_fma(sc.cz, rcur[v], nv);
                     pend_w[v] = nv;
                 }
@@ -491,35 +575,50 @@ k_rhs_central(const double* __restrict__ W, double* __restrict__ out, double* __
     flush();
 }
 
-template <int S>
-static hipError_t launch_rhs_S(const KGrid& g, const KGas& gas, const double* W, double* out,
-                               double* Rprev, const StepCoef* step, unsigned mask, hipStream_t st)
+// Tile shapes: FP64 keeps one wave per SIMD (registers), so a 64x4 tile
+// (64x2 for the eighth-order stencil, LDS); FP32 halves registers and LDS,
+// so 64x8 tiles with two waves per SIMD.
+template <int S, typename R>
+static hipError_t launch_rhs_SR(const KGrid& g, const KGas& gas, const double* W, double* out,
+                                double* Rprev, const StepCoef* step, unsigned mask, hipStream_t st)
 {
-    constexpr int TX = 64, TY = S <= 3 ? 4 : 2;
+    constexpr bool F32 = std::is_same<R, float>::value;
+    constexpr int TX = 64, TY = F32 ? (S <= 3 ? 8 : 4) : (S <= 3 ? 4 : 2);
+    constexpr int WPE = F32 ? 2 : 1;
     const int kc = g.nz;  // one march over the whole z extent per tile
     dim3 grid((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY, (g.nz + kc - 1) / kc);
     if (step) {
-        hipLaunchKernelGGL((k_rhs_central<S, TX, TY, true>), grid, dim3(TX * TY), 0, st, W, out,
-                           Rprev, g, gas, *step, (unsigned)SX_ALL, kc);
+        hipLaunchKernelGGL((k_rhs_central<S, TX, TY, WPE, R, true>), grid, dim3(TX * TY), 0, st, W,
+                           out, Rprev, g, gas, *step, (unsigned)SX_ALL, kc);
     } else {
         StepCoef none{0.0, 0.0, 0, 0};
-        hipLaunchKernelGGL((k_rhs_central<S, TX, TY, false>), grid, dim3(TX * TY), 0, st, W, out,
-                           Rprev, g, gas, none, mask, kc);
+        hipLaunchKernelGGL((k_rhs_central<S, TX, TY, WPE, R, false>), grid, dim3(TX * TY), 0, st, W,
+                           out, Rprev, g, gas, none, mask, kc);
     }
     return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t launch_rhs_R(const KGrid& g, const KGas& gas, const KScheme& sc, const double* W,
+                               double* out, double* Rprev, const StepCoef* step, unsigned mask,
+                               hipStream_t st)
+{
+    switch (sc.L) {
+    case 1: return launch_rhs_SR<1, R>(g, gas, W, out, Rprev, step, mask, st);
+    case 2: return launch_rhs_SR<2, R>(g, gas, W, out, Rprev, step, mask, st);
+    case 3: return launch_rhs_SR<3, R>(g, gas, W, out, Rprev, step, mask, st);
+    case 4: return launch_rhs_SR<4, R>(g, gas, W, out, Rprev, step, mask, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_rhs(const KGrid& g, const KGas& gas, const KScheme& sc, const double* W,
                       double* out, double* Rprev, const StepCoef* step, unsigned mask,
                       hipStream_t st)
 {
-    switch (sc.L) {
-    case 1: return launch_rhs_S<1>(g, gas, W, out, Rprev, step, mask, st);
-    case 2: return launch_rhs_S<2>(g, gas, W, out, Rprev, step, mask, st);
-    case 3: return launch_rhs_S<3>(g, gas, W, out, Rprev, step, mask, st);
-    case 4: return launch_rhs_S<4>(g, gas, W, out, Rprev, step, mask, st);
-    default: return hipErrorInvalidValue;
-    }
+    if (sc.precision == SX_FP32_FLUX)
+        return launch_rhs_R<float>(g, gas, sc, W, out, Rprev, step, mask, st);
+    return launch_rhs_R<double>(g, gas, sc, W, out, Rprev, step, mask, st);
 }
 
 }  // namespace sx

@@ -250,7 +250,7 @@ def shock_bl_fields(case: Case, noise: float = 0.03, deflection: float = 8.0,
     X = np.broadcast_to(x[None, None, :], shape)
     Y = np.broadcast_to(y[None, :, None], shape)
     above = Y > case.ly - X * math.tan(sh["beta"])
-    U2 = sh["M2"] * math.sqrt(sh["T21"])  # |u2| / U_inf with c_inf = 1/M
+    U2 = sh["M2"] * math.sqrt(sh["T21"]) / M  # |u2| / U_inf (c2 / c_inf = sqrt(T2/T1))
     th = math.radians(deflection)
     u = np.where(above, U2 * math.cos(th), u)
     v = np.where(above, -U2 * math.sin(th), v)

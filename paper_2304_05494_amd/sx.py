@@ -70,7 +70,8 @@ class sx_diag(ctypes.Structure):
 
 
 EXPORTS = ["sx_init", "sx_finalize", "sx_get_layout", "sx_bind", "sx_current", "sx_fill_ghosts",
-           "sx_rhs", "sx_rk3_step", "sx_compute_dt", "sx_diagnostics", "sx_timing_enable",
+           "sx_rhs", "sx_rk3_step", "sx_compute_dt", "sx_diagnostics", "sx_set_flag_override",
+           "sx_timing_enable",
            "sx_timing_read", "sx_last_error"]
 
 _lib = None
@@ -99,6 +100,7 @@ def load() -> ctypes.CDLL:
     L.sx_rk3_step.argtypes = [H, ctypes.c_double]
     L.sx_compute_dt.argtypes = [H, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
     L.sx_diagnostics.argtypes = [H, dp, ctypes.POINTER(sx_diag)]
+    L.sx_set_flag_override.argtypes = [H, dp, dp, dp]
     L.sx_timing_enable.argtypes = [H, ctypes.c_int]
     L.sx_timing_read.argtypes = [H, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double)]
     L.sx_last_error.argtypes = [H]
@@ -225,6 +227,16 @@ class Handle:
         dt = ctypes.c_double()
         self._check(self.lib.sx_compute_dt(self.h, cfl, ctypes.byref(dt)))
         return dt.value
+
+    def sx_set_flag_override(self, flags=None):
+        """flags = (fx, fy, fz) uint8 arrays/tensors in the face layout, or
+        None to return to the sensor."""
+        if flags is None:
+            self._check(self.lib.sx_set_flag_override(self.h, None, None, None))
+            return
+        import numpy as _np
+        arrs = [_np.ascontiguousarray(f, dtype=_np.uint8) for f in flags]
+        self._check(self.lib.sx_set_flag_override(self.h, *[a.ctypes.data for a in arrs]))
 
     def sx_timing_enable(self, enable: bool = True):
         self._check(self.lib.sx_timing_enable(self.h, int(enable)))
