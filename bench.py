@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--cpu-sample-steps", type=int, default=1)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain device copy of 2 GiB (counter calibration)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-form legs")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON autotune cache of the batched form (default: tune afresh)")
     return ap.parse_args()
 
 
@@ -96,6 +99,48 @@ def cpu_baseline(case, Wn, dt, steps):
                       f"({el:.1f} s, OpenMP over z-planes)"}
 
 
+def bench_batch(args, precision, fields=None):
+    """The batched form: 48 uneven periodic blocks (TGV / decaying
+    turbulence, 32^3 .. 128x64x64), one persistent launch per substep, the
+    step replayed from a captured graph, work-item shape autotuned."""
+    import numpy as np
+    import torch
+    from paper_2304_05494_amd import inputs, sx
+    cases = inputs.batch_cases(48)
+    if fields is None:
+        fields = [np.ascontiguousarray(inputs.fields(c)) for c in cases]
+    bh = sx.BatchHandle(cases, precision)
+    bh.sx_bind(bh.to_arena(fields))
+    t = bh.sx_autotune(args.tune_cache)
+    dt = bh.sx_compute_dt(0.5)
+    for _ in range(args.warmup):
+        bh.sx_rk3_step(dt)
+    torch.cuda.synchronize()
+    bh.sx_timing_enable(True)
+    bh.sx_timing_read()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(args.steps):
+        bh.sx_rk3_step(dt)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / args.steps
+    n, kms = bh.sx_timing_read()
+    d = bh.sx_diagnostics()
+    pts = sum(c.points for c in cases)
+    alg = ALG_BYTES_PER_POINT_STEP / SUBSTEPS * pts
+    out = {
+        "value": pts / (ms * 1e-3), "ms_per_step": ms, "blocks": len(cases), "points": pts,
+        "launch_ms": kms / n, "roofline_frac": alg / (kms / n * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "tiling": {"tile_x": t.tile_x, "tile_y": t.tile_y, "zchunk": t.zchunk,
+                   "workgroups": t.workgroups, "work_items": t.work_items},
+        "graph": True, "state_ok": d.status == sx.SX_OK,
+    }
+    del bh
+    torch.cuda.empty_cache()
+    return out, fields
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -141,7 +186,7 @@ def main():
     avg_launch_s = kern_ms / launches * 1e-3
     alg_bytes_launch = ALG_BYTES_PER_POINT_STEP / SUBSTEPS * case.points
     achieved = alg_bytes_launch / avg_launch_s / 1e9
-    kernel = "k_rhs_central<3,64,4,true>"
+    kernel = "k_rhs_central<3, 64, 4, 1, double, true, false>"
     traffic = load_traffic(kernel)
     line = {
         "metric": "grid-point updates/s per RK3 step (FP64 vs FP32-flux) + % HBM roofline",
@@ -205,6 +250,14 @@ def main():
         "roofline_frac": ALG_BYTES_PER_POINT_STEP / SUBSTEPS * case.points / (k32 / n32 * 1e-3) / 1e9 / HBM_PEAK_GBS,
     }
     del h32, W32
+    if not args.no_batch:
+        b64, bf = bench_batch(args, sx.SX_FP64)
+        b32, _ = bench_batch(args, sx.SX_FP32_FLUX, bf)
+        b32["speedup_vs_fp64"] = b64["ms_per_step"] / b32["ms_per_step"]
+        line["batched"] = {"workload": "48 periodic blocks (seed 5; sizes 32^3, 48^3, 64^3, 96^3, "
+                                       "128x64x64; TGV or decaying turbulence; Mach 0.1-0.5), "
+                                       "C6 + V6, one graph-replayed persistent launch per substep",
+                           "fp64": b64, "fp32_flux": b32}
     if not args.no_cpu_baseline:
         del h, W0
         torch.cuda.empty_cache()

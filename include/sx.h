@@ -197,6 +197,71 @@ int sx_set_flag_override(sx_handle* h, const unsigned char* fx, const unsigned c
 int sx_timing_enable(sx_handle* h, int enable);
 int sx_timing_read(sx_handle* h, long long* launches, double* total_ms);
 
+/* ---- Batched form ---------------------------------------------------------
+ * Many independent blocks of uneven size advanced together: one persistent
+ * launch per RK3 substep works through a list of (block, column tile,
+ * z-chunk) work items, and the three substeps of a step are captured in a
+ * HIP graph that sx_rk3_step replays. This is the throughput analogue of the
+ * paper's many-block-per-device runs and of its launch-shape tuning
+ * (Sections 3.3-3.4); every block follows the single-block equations.
+ *
+ * Every block must be periodic on all six faces (the kernel writes the
+ * periodic ghost images, so no ghost-fill launches sit between substeps),
+ * at least twice the ghost width in every direction, and share one scheme
+ * (sensor off). A batch handle is used with the generic calls:
+ *   sx_get_layout  elems = length of one state arena (doubles); interior =
+ *                  length of the RK-register arena / 5 (rounded up);
+ *   sx_bind        W0, W1 = state arenas, Rprev = register arena; block b's
+ *                  state is the single-block layout of its own size at
+ *                  w_offset (sx_get_box), its register [5][nz][ny][nx] at
+ *                  r_offset. Ghosts of W0 are filled by the library;
+ *   sx_rk3_step    replays the step graph (captured on first use per
+ *                  starting buffer, and again after sx_bind/sx_set_tiling;
+ *                  dt lives in device memory, so a new dt needs no capture);
+ *   sx_rhs         R = register-layout arena, per-block launches;
+ *   sx_compute_dt  min over blocks; sx_diagnostics: sums over blocks of the
+ *                  sums and counts, max/min over blocks of the extrema.
+ * With timing on, each recorded interval spans one whole step (three
+ * substep launches) and sx_timing_read counts three launches per step.
+ * Returns SX_EUNSUPPORTED for non-periodic blocks, a sensor, or blocks
+ * smaller than twice the ghost width; SX_EINVAL for other bad input. */
+int sx_init_batch(int nbox, const sx_grid* grids, const sx_gas* gases, const sx_scheme* scheme,
+                  sx_handle** out);
+
+/* Layout and arena offsets (doubles) of block `box`. SX_EINVAL for a
+ * single-block handle or an index out of range. */
+int sx_get_box(const sx_handle* h, int box, sx_layout* lay, long long* w_offset,
+               long long* r_offset);
+
+/* Work-item shape of the persistent launch. */
+typedef struct {
+    int tile_x;               /* column-tile width: 64 or 32 (in: selects shape) */
+    int tile_y;               /* column-tile height (out: follows from tile_x) */
+    int zchunk;               /* at most this many planes per work item; each
+                                 block's z extent is cut into equal chunks */
+    int workgroups;           /* persistent workgroups (in: 0 = fill the device) */
+    int work_items;           /* out: number of work items */
+    double ms_per_substep;    /* out of sx_autotune: measured (or cached) time */
+} sx_tiling;
+
+/* Sets / reads the work-item shape (host-synchronous; drops the captured
+ * graphs). SX_ESTATE on a single-block handle. */
+int sx_set_tiling(sx_handle* h, const sx_tiling* t);
+int sx_get_tiling(const sx_handle* h, sx_tiling* t);
+
+/* Picks the work-item shape by timing substep launches over the candidate
+ * tile widths and z-chunks, then applies it. With cache_path non-NULL the
+ * choice is looked up in (and, after timing, written to) a JSON file keyed
+ * by device, precision, order and the multiset of block sizes. Needs bound
+ * buffers; the current state is left unchanged, the inactive state buffer
+ * and the register arena are overwritten (the next step overwrites both
+ * before reading them). Host-synchronous. */
+int sx_autotune(sx_handle* h, const char* cache_path, sx_tiling* chosen);
+
+/* Batch handles: 1 (default) replays the captured step graph, 0 launches
+ * the three substeps directly. The results are identical. */
+int sx_set_graph(sx_handle* h, int enable);
+
 /* Message of the last failing call on this handle ("" if none). */
 const char* sx_last_error(const sx_handle* h);
 

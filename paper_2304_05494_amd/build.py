@@ -15,14 +15,14 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsx.so")
-SOURCES = ["sx_api.hip", "sx_ghost.hip", "sx_rhs.hip", "sx_reduce.hip", "sx_weno.hip"]
+SOURCES = ["sx_api.hip", "sx_ghost.hip", "sx_rhs.hip", "sx_reduce.hip", "sx_weno.hip", "sx_batch.hip"]
 ARCH = os.environ.get("SX_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-ffp-contract=fast", "-munsafe-fp-atomics",
+    "-ffp-contract=on", "-munsafe-fp-atomics",
     "-Wall", "-Wno-unused-function",
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]

@@ -7,46 +7,15 @@
 #include <utility>
 #include <vector>
 
-#include "sx_internal.h"
+#include "sx_handle.h"
 
-struct sx_handle {
-    sx_grid grid;
-    sx_gas gas;
-    sx_scheme scheme;
-    sx_layout lay;
-    sx::KGrid kg;
-    sx::KGas kgas;
-    sx::KScheme ks;
-    double* d_metrics = nullptr;  // eta_y, eta_yy, y_eta  (3*ny)
-    double* d_scratch = nullptr;  // reduction partials + results
-    // hybrid scheme (sensor on): theta, face flags, list of corrected nodes
-    double* d_theta = nullptr;
-    unsigned char* d_fx = nullptr;
-    unsigned char* d_fy = nullptr;
-    unsigned char* d_fz = nullptr;
-    int* d_list = nullptr;
-    int* d_count = nullptr;
-    unsigned long long* d_fcount = nullptr;
-    int flag_override = 0;
-    double* W[2] = {nullptr, nullptr};
-    double* Rprev = nullptr;
-    hipStream_t st = nullptr;
-    int cur = 0;
-    bool bound = false;
-    bool timing = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free;
-    std::string err;
-};
-
-namespace {
-
-int fail(sx_handle* h, int code, const char* msg)
+int sx_fail(sx_handle* h, int code, const char* msg)
 {
     if (h) h->err = msg;
     return code;
 }
 
-int hip_fail(sx_handle* h, hipError_t e, const char* where)
+int sx_hip_fail(sx_handle* h, hipError_t e, const char* where)
 {
     if (h) {
         char buf[256];
@@ -55,6 +24,8 @@ int hip_fail(sx_handle* h, hipError_t e, const char* where)
     }
     return SX_EHIP;
 }
+
+namespace {
 
 // y node coordinate of index j (ghost indices continue the mapping).
 double y_node(const sx_grid& g, int j)
@@ -70,9 +41,34 @@ double y_node(const sx_grid& g, int j)
     return g.y0 + j * (g.ly / g.ny);
 }
 
+bool valid_order(int o) { return o == 2 || o == 4 || o == 6 || o == 8; }
+
+}  // namespace
+
+// Event pair around launches on the bound stream (timing mode).
+hipError_t sx_timed_begin(sx_handle* h, std::pair<hipEvent_t, hipEvent_t>* ev)
+{
+    if (!h->ev_free.empty()) {
+        *ev = h->ev_free.back();
+        h->ev_free.pop_back();
+    } else {
+        hipError_t e = hipEventCreate(&ev->first);
+        if (e != hipSuccess) return e;
+        e = hipEventCreate(&ev->second);
+        if (e != hipSuccess) return e;
+    }
+    return hipEventRecord(ev->first, h->st);
+}
+
+hipError_t sx_timed_end(sx_handle* h, const std::pair<hipEvent_t, hipEvent_t>& ev)
+{
+    h->ev_used.push_back(ev);
+    return hipEventRecord(ev.second, h->st);
+}
+
 // Host metrics: y_eta = D1(y), y_etaeta = D2(y) with the central stencil of
 // half-order L applied to the node coordinates (unit eta spacing).
-void host_metrics(const sx_grid& g, int L, double* y_eta, double* y_ee)
+void sx_host_metrics(const sx_grid& g, int L, double* y_eta, double* y_ee)
 {
     static const double A[5][5] = {{0}, {0, 0.5}, {0, 2.0 / 3.0, -1.0 / 12.0},
                                    {0, 0.75, -0.15, 1.0 / 60.0},
@@ -98,45 +94,15 @@ void host_metrics(const sx_grid& g, int L, double* y_eta, double* y_ee)
     }
 }
 
-bool valid_order(int o) { return o == 2 || o == 4 || o == 6 || o == 8; }
-
-hipError_t timed_begin(sx_handle* h, std::pair<hipEvent_t, hipEvent_t>* ev)
+// Validates one block description; returns SX_OK and the ghost width.
+int sx_validate(const sx_grid& g, const sx_gas& gas, const sx_scheme& s, int* ng_out)
 {
-    if (!h->ev_free.empty()) {
-        *ev = h->ev_free.back();
-        h->ev_free.pop_back();
-    } else {
-        hipError_t e = hipEventCreate(&ev->first);
-        if (e != hipSuccess) return e;
-        e = hipEventCreate(&ev->second);
-        if (e != hipSuccess) return e;
-    }
-    return hipEventRecord(ev->first, h->st);
-}
-
-hipError_t timed_end(sx_handle* h, const std::pair<hipEvent_t, hipEvent_t>& ev)
-{
-    h->ev_used.push_back(ev);
-    return hipEventRecord(ev.second, h->st);
-}
-
-}  // namespace
-
-extern "C" {
-
-int sx_init(const sx_grid* grid, const sx_gas* gas, const sx_scheme* scheme, sx_handle** out)
-{
-    if (!out) return SX_EINVAL;
-    *out = nullptr;
-    if (!grid || !gas || !scheme) return SX_EINVAL;
-    const sx_grid& g = *grid;
-    const sx_scheme& s = *scheme;
     if (!valid_order(s.central_order) || !valid_order(s.visc_order)) return SX_EINVAL;
     if (s.weno_order != 1 && s.weno_order != 3 && s.weno_order != 5) return SX_EINVAL;
     if (s.visc_order != s.central_order) return SX_EUNSUPPORTED;
     if (s.sensor != 0 && s.sensor != 1) return SX_EINVAL;
     if (s.precision != SX_FP64 && s.precision != SX_FP32_FLUX) return SX_EINVAL;
-    if (!(gas->gamma > 1.0) || !(gas->mach > 0.0) || !(gas->reynolds > 0.0) || !(gas->prandtl > 0.0))
+    if (!(gas.gamma > 1.0) || !(gas.mach > 0.0) || !(gas.reynolds > 0.0) || !(gas.prandtl > 0.0))
         return SX_EINVAL;
     if (!(g.lx > 0.0) || !(g.ly > 0.0) || !(g.lz > 0.0)) return SX_EINVAL;
     if (g.ymap < SX_Y_UNIFORM || g.ymap > SX_Y_TANH1) return SX_EINVAL;
@@ -151,84 +117,112 @@ int sx_init(const sx_grid* grid, const sx_gas* gas, const sx_scheme* scheme, sx_
             if (g.bc[2 * d + sd] < SX_BC_PERIODIC || g.bc[2 * d + sd] > SX_BC_FROZEN) return SX_EINVAL;
         if ((g.bc[2 * d] == SX_BC_PERIODIC) != (g.bc[2 * d + 1] == SX_BC_PERIODIC)) return SX_EINVAL;
     }
+    *ng_out = ng;
+    return SX_OK;
+}
 
-    sx_handle* h = new sx_handle();
-    h->grid = g;
-    h->gas = *gas;
-    h->scheme = s;
-    sx_layout& lay = h->lay;
-    lay.ng = ng;
-    lay.ox = 16;
-    lay.px = ((lay.ox + g.nx + ng + 15) / 16) * 16;
-    lay.py = g.ny + 2 * ng;
-    lay.pz = g.nz + 2 * ng;
-    lay.var_stride = lay.px * lay.py * lay.pz;
-    lay.elems = 5 * lay.var_stride;
-    lay.interior = (long long)g.nx * g.ny * g.nz;
-    if (lay.elems >= (1LL << 40)) {
-        delete h;
-        return SX_EINVAL;
-    }
+void sx_fill_kernel_params(const sx_grid& g, const sx_gas& gas, const sx_scheme& s, int ng,
+                           sx_layout* lay, sx::KGrid* kg, sx::KGas* kgas, sx::KScheme* ks)
+{
+    lay->ng = ng;
+    lay->ox = 16;
+    lay->px = ((lay->ox + g.nx + ng + 15) / 16) * 16;
+    lay->py = g.ny + 2 * ng;
+    lay->pz = g.nz + 2 * ng;
+    lay->var_stride = lay->px * lay->py * lay->pz;
+    lay->elems = 5 * lay->var_stride;
+    lay->interior = (long long)g.nx * g.ny * g.nz;
 
-    sx::KGrid& kg = h->kg;
-    kg.nx = g.nx;
-    kg.ny = g.ny;
-    kg.nz = g.nz;
-    kg.ng = ng;
-    kg.ox = lay.ox;
-    kg.sy = lay.px;
-    kg.sz = lay.px * lay.py;
-    kg.sv = lay.var_stride;
-    kg.base = ng * kg.sz + ng * kg.sy + lay.ox;
-    kg.nint = lay.interior;
-    for (int f = 0; f < 6; ++f) kg.bc[f] = g.bc[f];
-    kg.dx = g.lx / g.nx;
-    kg.dz = g.lz / g.nz;
-    kg.dxi = 1.0 / kg.dx;
-    kg.dzi = 1.0 / kg.dz;
+    kg->nx = g.nx;
+    kg->ny = g.ny;
+    kg->nz = g.nz;
+    kg->ng = ng;
+    kg->ox = lay->ox;
+    kg->sy = lay->px;
+    kg->sz = lay->px * lay->py;
+    kg->sv = lay->var_stride;
+    kg->base = ng * kg->sz + ng * kg->sy + lay->ox;
+    kg->nint = lay->interior;
+    for (int f = 0; f < 6; ++f) kg->bc[f] = g.bc[f];
+    kg->dx = g.lx / g.nx;
+    kg->dz = g.lz / g.nz;
+    kg->dxi = 1.0 / kg->dx;
+    kg->dzi = 1.0 / kg->dz;
 
-    sx::KGas& kgas = h->kgas;
-    kgas.gamma = gas->gamma;
-    kgas.gm1 = gas->gamma - 1.0;
-    kgas.gM2 = gas->gamma * gas->mach * gas->mach;
-    kgas.igM2 = 1.0 / kgas.gM2;
-    kgas.cp = 1.0 / (kgas.gm1 * gas->mach * gas->mach);
-    kgas.s = gas->visc_exp;
-    kgas.ire = 1.0 / gas->reynolds;
-    kgas.ipr = 1.0 / gas->prandtl;
-    kgas.t_wall = gas->t_wall;
-    kgas.pref = kgas.igM2;
-    kgas.href = kgas.cp;
+    kgas->gamma = gas.gamma;
+    kgas->gm1 = gas.gamma - 1.0;
+    kgas->gM2 = gas.gamma * gas.mach * gas.mach;
+    kgas->igM2 = 1.0 / kgas->gM2;
+    kgas->cp = 1.0 / (kgas->gm1 * gas.mach * gas.mach);
+    kgas->s = gas.visc_exp;
+    kgas->ire = 1.0 / gas.reynolds;
+    kgas->ipr = 1.0 / gas.prandtl;
+    kgas->t_wall = gas.t_wall;
+    kgas->pref = kgas->igM2;
+    kgas->href = kgas->cp;
 
-    sx::KScheme& ks = h->ks;
-    ks.L = L;
-    ks.Lv = Lv;
-    ks.r = r;
-    ks.sensor = s.sensor;
-    ks.sensor_thr = s.sensor_thr;
-    ks.sensor_eps = s.sensor_eps;
-    ks.weno_eps = s.weno_eps;
-    ks.precision = s.precision;
+    ks->L = s.central_order / 2;
+    ks->Lv = s.visc_order / 2;
+    ks->r = (s.weno_order + 1) / 2;
+    ks->sensor = s.sensor;
+    ks->sensor_thr = s.sensor_thr;
+    ks->sensor_eps = s.sensor_eps;
+    ks->weno_eps = s.weno_eps;
+    ks->precision = s.precision;
+}
 
-    // metrics on the host, uploaded once
+// Metrics of one block on the host, uploaded; sets the KGrid pointers.
+hipError_t sx_upload_metrics(const sx_grid& g, int L, double** d_metrics, sx::KGrid* kg)
+{
     const int ny = g.ny;
-    double* hm = new double[3 * ny];
-    double* yee = new double[ny];
-    host_metrics(g, L, hm + 2 * ny, yee);
+    std::vector<double> hm(3 * ny), yee(ny);
+    sx_host_metrics(g, L, hm.data() + 2 * ny, yee.data());
     for (int j = 0; j < ny; ++j) {
         const double ye = hm[2 * ny + j];
         hm[j] = 1.0 / ye;
         hm[ny + j] = -yee[j] / (ye * ye * ye);
     }
-    delete[] yee;
-    hipError_t e = hipMalloc(&h->d_metrics, sizeof(double) * 3 * ny);
-    if (e == hipSuccess)
-        e = hipMemcpy(h->d_metrics, hm, sizeof(double) * 3 * ny, hipMemcpyHostToDevice);
-    delete[] hm;
+    hipError_t e = hipMalloc(d_metrics, sizeof(double) * 3 * ny);
+    if (e == hipSuccess) e = hipMemcpy(*d_metrics, hm.data(), sizeof(double) * 3 * ny, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        kg->eta_y = *d_metrics;
+        kg->eta_yy = *d_metrics + ny;
+        kg->y_eta = *d_metrics + 2 * ny;
+    }
+    return e;
+}
+
+extern "C" {
+
+int sx_init(const sx_grid* grid, const sx_gas* gas, const sx_scheme* scheme, sx_handle** out)
+{
+    if (!out) return SX_EINVAL;
+    *out = nullptr;
+    if (!grid || !gas || !scheme) return SX_EINVAL;
+    const sx_grid& g = *grid;
+    const sx_scheme& s = *scheme;
+    int ng = 0;
+    const int rc = sx_validate(g, *gas, s, &ng);
+    if (rc != SX_OK) return rc;
+
+    sx_handle* h = new sx_handle();
+    h->grid = g;
+    h->gas = *gas;
+    h->scheme = s;
+    sx_fill_kernel_params(g, *gas, s, ng, &h->lay, &h->kg, &h->kgas, &h->ks);
+    if (h->lay.elems >= (1LL << 40)) {
+        delete h;
+        return SX_EINVAL;
+    }
+    bool all_periodic = true;
+    for (int f = 0; f < 6; ++f) all_periodic = all_periodic && g.bc[f] == SX_BC_PERIODIC;
+    h->pimg = all_periodic && !s.sensor && g.nx >= 2 * ng && g.ny >= 2 * ng && g.nz >= 2 * ng;
+
+    hipError_t e = sx_upload_metrics(g, h->ks.L, &h->d_metrics, &h->kg);
     if (e == hipSuccess)
         e = hipMalloc(&h->d_scratch, sizeof(double) * (sx::kReduceBlocks + 1) * sx::kDiagVals);
     if (e == hipSuccess && s.sensor) {
-        const long long ni = lay.interior;
+        const long long ni = h->lay.interior;
         e = hipMalloc(&h->d_theta, sizeof(double) * ni);
         if (e == hipSuccess) e = hipMalloc(&h->d_fx, (size_t)g.nz * g.ny * (g.nx + 1));
         if (e == hipSuccess) e = hipMalloc(&h->d_fy, (size_t)g.nz * (g.ny + 1) * g.nx);
@@ -241,9 +235,6 @@ int sx_init(const sx_grid* grid, const sx_gas* gas, const sx_scheme* scheme, sx_
         sx_finalize(h);
         return e == hipErrorOutOfMemory ? SX_ENOMEM : SX_EHIP;
     }
-    kg.eta_y = h->d_metrics;
-    kg.eta_yy = h->d_metrics + ny;
-    kg.y_eta = h->d_metrics + 2 * ny;
     *out = h;
     return SX_OK;
 }
@@ -251,16 +242,16 @@ int sx_init(const sx_grid* grid, const sx_gas* gas, const sx_scheme* scheme, sx_
 void sx_finalize(sx_handle* h)
 {
     if (!h) return;
-    if (h->d_metrics) (void)hipFree(h->d_metrics);
-    if (h->d_scratch) (void)hipFree(h->d_scratch);
-    for (void* p : {(void*)h->d_theta, (void*)h->d_fx, (void*)h->d_fy, (void*)h->d_fz,
-                    (void*)h->d_list, (void*)h->d_count, (void*)h->d_fcount})
+    for (void* p : {(void*)h->d_metrics, (void*)h->d_scratch, (void*)h->d_theta, (void*)h->d_fx,
+                    (void*)h->d_fy, (void*)h->d_fz, (void*)h->d_list, (void*)h->d_count,
+                    (void*)h->d_fcount})
         if (p) (void)hipFree(p);
     for (auto* v : {&h->ev_used, &h->ev_free})
         for (auto& p : *v) {
             (void)hipEventDestroy(p.first);
             (void)hipEventDestroy(p.second);
         }
+    if (h->batch) sx_batch_free(h);
     delete h;
 }
 
@@ -274,18 +265,27 @@ int sx_get_layout(const sx_handle* h, sx_layout* out)
 int sx_bind(sx_handle* h, double* W0, double* W1, double* Rprev, void* stream)
 {
     if (!h) return SX_EINVAL;
-    if (!W0 || !W1 || !Rprev || W0 == W1) return fail(h, SX_EINVAL, "sx_bind: null or aliased buffer");
+    if (!W0 || !W1 || !Rprev || W0 == W1) return sx_fail(h, SX_EINVAL, "sx_bind: null or aliased buffer");
     if (((uintptr_t)W0 | (uintptr_t)W1 | (uintptr_t)Rprev) & 255)
-        return fail(h, SX_EINVAL, "sx_bind: buffers must be 256-byte aligned");
+        return sx_fail(h, SX_EINVAL, "sx_bind: buffers must be 256-byte aligned");
     h->W[0] = W0;
     h->W[1] = W1;
     h->Rprev = Rprev;
     h->st = (hipStream_t)stream;
     h->cur = 0;
+    h->ghosts_valid[0] = h->ghosts_valid[1] = false;
+    if (h->batch) {
+        const int rc = sx_batch_bind(h);
+        if (rc == SX_OK) {
+            h->bound = true;
+            h->err.clear();
+        }
+        return rc;
+    }
     hipError_t e = hipMemcpyAsync(W1, W0, sizeof(double) * h->lay.elems, hipMemcpyDeviceToDevice, h->st);
     if (e == hipSuccess)
         e = hipMemsetAsync(Rprev, 0, sizeof(double) * 5 * h->lay.interior, h->st);
-    if (e != hipSuccess) return hip_fail(h, e, "sx_bind");
+    if (e != hipSuccess) return sx_hip_fail(h, e, "sx_bind");
     h->bound = true;
     h->err.clear();
     return SX_OK;
@@ -301,19 +301,24 @@ int sx_current(const sx_handle* h, int* which)
 int sx_fill_ghosts(sx_handle* h, double* W)
 {
     if (!h) return SX_EINVAL;
-    if (!W) return fail(h, SX_EINVAL, "sx_fill_ghosts: null state");
+    if (!W) return sx_fail(h, SX_EINVAL, "sx_fill_ghosts: null state");
+    if (h->batch) return sx_batch_fill_ghosts(h, W);
     hipError_t e = sx::launch_ghost_fill(h->kg, h->kgas, W, h->st);
-    if (e != hipSuccess) return hip_fail(h, e, "sx_fill_ghosts");
+    if (e != hipSuccess) return sx_hip_fail(h, e, "sx_fill_ghosts");
+    for (int b = 0; b < 2; ++b)
+        if (W == h->W[b]) h->ghosts_valid[b] = true;
     return SX_OK;
 }
 
 int sx_rhs(sx_handle* h, double* W, double* R, unsigned term_mask)
 {
     if (!h) return SX_EINVAL;
-    if (!W || !R || W == R) return fail(h, SX_EINVAL, "sx_rhs: null or aliased buffer");
-    if (term_mask & ~(unsigned)SX_ALL) return fail(h, SX_EINVAL, "sx_rhs: unknown term bits");
+    if (!W || !R || W == R) return sx_fail(h, SX_EINVAL, "sx_rhs: null or aliased buffer");
+    if (term_mask & ~(unsigned)SX_ALL) return sx_fail(h, SX_EINVAL, "sx_rhs: unknown term bits");
+    if (h->batch) return sx_batch_rhs(h, W, R, term_mask);
     hipError_t e = sx::launch_ghost_fill(h->kg, h->kgas, W, h->st);
-    if (e == hipSuccess) e = sx::launch_rhs(h->kg, h->kgas, h->ks, W, R, nullptr, nullptr, term_mask, h->st);
+    if (e == hipSuccess)
+        e = sx::launch_rhs(h->kg, h->kgas, h->ks, W, R, nullptr, nullptr, term_mask, false, h->st);
     if (e == hipSuccess && h->ks.sensor && (term_mask & (SX_CONV_X | SX_CONV_Y | SX_CONV_Z))) {
         e = sx::launch_sensor_flags(h->kg, h->ks, W, h->d_theta, h->d_fx, h->d_fy, h->d_fz,
                                     h->flag_override, h->d_list, h->d_count, h->st);
@@ -321,7 +326,9 @@ int sx_rhs(sx_handle* h, double* W, double* R, unsigned term_mask)
             e = sx::launch_weno(h->kg, h->kgas, h->ks, term_mask, W, h->d_fx, h->d_fy, h->d_fz,
                                 h->d_list, h->d_count, 0, 0.0, 0, R, nullptr, h->st);
     }
-    if (e != hipSuccess) return hip_fail(h, e, "sx_rhs");
+    if (e != hipSuccess) return sx_hip_fail(h, e, "sx_rhs");
+    for (int b = 0; b < 2; ++b)
+        if (W == h->W[b]) h->ghosts_valid[b] = true;
     return SX_OK;
 }
 
@@ -330,18 +337,20 @@ int sx_rk3_step(sx_handle* h, double dt)
     static const double gk[3] = {8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0};
     static const double zk[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
     if (!h) return SX_EINVAL;
-    if (!h->bound) return fail(h, SX_ESTATE, "sx_rk3_step: no buffers bound");
-    if (!(dt > 0.0) || !isfinite(dt)) return fail(h, SX_EINVAL, "sx_rk3_step: dt must be positive");
+    if (!h->bound) return sx_fail(h, SX_ESTATE, "sx_rk3_step: no buffers bound");
+    if (!(dt > 0.0) || !isfinite(dt)) return sx_fail(h, SX_EINVAL, "sx_rk3_step: dt must be positive");
+    if (h->batch) return sx_batch_step(h, dt);
     for (int s = 0; s < 3; ++s) {
         double* src = h->W[h->cur];
         double* dst = h->W[1 - h->cur];
         sx::StepCoef sc{dt * gk[s], dt * zk[s], s > 0 ? 1 : 0, s < 2 ? 1 : 0};
-        hipError_t e = sx::launch_ghost_fill(h->kg, h->kgas, src, h->st);
+        hipError_t e = hipSuccess;
+        if (!h->pimg || !h->ghosts_valid[h->cur]) e = sx::launch_ghost_fill(h->kg, h->kgas, src, h->st);
         std::pair<hipEvent_t, hipEvent_t> ev{};
-        if (e == hipSuccess && h->timing) e = timed_begin(h, &ev);
+        if (e == hipSuccess && h->timing) e = sx_timed_begin(h, &ev);
         if (e == hipSuccess)
-            e = sx::launch_rhs(h->kg, h->kgas, h->ks, src, dst, h->Rprev, &sc, SX_ALL, h->st);
-        if (e == hipSuccess && h->timing) e = timed_end(h, ev);
+            e = sx::launch_rhs(h->kg, h->kgas, h->ks, src, dst, h->Rprev, &sc, SX_ALL, h->pimg, h->st);
+        if (e == hipSuccess && h->timing) e = sx_timed_end(h, ev);
         if (e == hipSuccess && h->ks.sensor) {
             e = sx::launch_sensor_flags(h->kg, h->ks, src, h->d_theta, h->d_fx, h->d_fy, h->d_fz,
                                         h->flag_override, h->d_list, h->d_count, h->st);
@@ -350,7 +359,9 @@ int sx_rk3_step(sx_handle* h, double dt)
                                     h->d_list, h->d_count, 1, sc.cg, sc.write_prev, dst, h->Rprev,
                                     h->st);
         }
-        if (e != hipSuccess) return hip_fail(h, e, "sx_rk3_step");
+        if (e != hipSuccess) return sx_hip_fail(h, e, "sx_rk3_step");
+        h->ghosts_valid[h->cur] = true;
+        h->ghosts_valid[1 - h->cur] = h->pimg;
         h->cur = 1 - h->cur;
     }
     return SX_OK;
@@ -359,16 +370,17 @@ int sx_rk3_step(sx_handle* h, double dt)
 int sx_compute_dt(sx_handle* h, double cfl, double* dt)
 {
     if (!h || !dt) return SX_EINVAL;
-    if (!h->bound) return fail(h, SX_ESTATE, "sx_compute_dt: no buffers bound");
-    if (!(cfl > 0.0)) return fail(h, SX_EINVAL, "sx_compute_dt: cfl must be positive");
+    if (!h->bound) return sx_fail(h, SX_ESTATE, "sx_compute_dt: no buffers bound");
+    if (!(cfl > 0.0)) return sx_fail(h, SX_EINVAL, "sx_compute_dt: cfl must be positive");
+    if (h->batch) return sx_batch_dt(h, cfl, dt);
     const int nb = sx::kReduceBlocks;
     double rate = 0.0;
     hipError_t e = sx::launch_max_rate(h->kg, h->kgas, h->W[h->cur], h->d_scratch, nb, h->st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(&rate, h->d_scratch + nb, sizeof(double), hipMemcpyDeviceToHost, h->st);
     if (e == hipSuccess) e = hipStreamSynchronize(h->st);
-    if (e != hipSuccess) return hip_fail(h, e, "sx_compute_dt");
-    if (!(rate > 0.0) || !isfinite(rate)) return fail(h, SX_ENONFINITE, "sx_compute_dt: rate not finite");
+    if (e != hipSuccess) return sx_hip_fail(h, e, "sx_compute_dt");
+    if (!(rate > 0.0) || !isfinite(rate)) return sx_fail(h, SX_ENONFINITE, "sx_compute_dt: rate not finite");
     *dt = cfl / rate;
     return SX_OK;
 }
@@ -376,31 +388,36 @@ int sx_compute_dt(sx_handle* h, double cfl, double* dt)
 int sx_diagnostics(sx_handle* h, const double* R, sx_diag* out)
 {
     if (!h || !out) return SX_EINVAL;
-    if (!h->bound) return fail(h, SX_ESTATE, "sx_diagnostics: no buffers bound");
-    const int nb = sx::kReduceBlocks;
+    if (!h->bound) return sx_fail(h, SX_ESTATE, "sx_diagnostics: no buffers bound");
     double v[sx::kDiagVals];
-    hipError_t e = sx::launch_diagnostics(h->kg, h->kgas, h->ks, h->W[h->cur], R, h->d_scratch, nb, h->st);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(v, h->d_scratch + (long long)nb * sx::kDiagVals, sizeof v,
-                           hipMemcpyDeviceToHost, h->st);
-    unsigned long long fc[3] = {0, 0, 0};
-    if (e == hipSuccess && h->ks.sensor) {
-        double* Wc = h->W[h->cur];
-        e = sx::launch_ghost_fill(h->kg, h->kgas, Wc, h->st);
+    if (h->batch) {
+        const int rc = sx_batch_diagnostics(h, R, v);
+        if (rc != SX_OK) return rc;
+    } else {
+        const int nb = sx::kReduceBlocks;
+        hipError_t e = sx::launch_diagnostics(h->kg, h->kgas, h->ks, h->W[h->cur], R, h->d_scratch, nb, h->st);
         if (e == hipSuccess)
-            e = sx::launch_sensor_flags(h->kg, h->ks, Wc, h->d_theta, h->d_fx, h->d_fy, h->d_fz,
-                                        h->flag_override, h->d_list, h->d_count, h->st);
-        if (e == hipSuccess) e = sx::launch_count_flags(h->kg, h->d_fx, h->d_fy, h->d_fz, h->d_fcount, h->st);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(fc, h->d_fcount, sizeof fc, hipMemcpyDeviceToHost, h->st);
-    }
-    if (e == hipSuccess) e = hipStreamSynchronize(h->st);
-    if (e != hipSuccess) return hip_fail(h, e, "sx_diagnostics");
-    if (h->ks.sensor) {
-        const sx_grid& g = h->grid;
-        v[12] = (double)fc[0] / ((double)g.nz * g.ny * (g.nx + 1));
-        v[13] = (double)fc[1] / ((double)g.nz * (g.ny + 1) * g.nx);
-        v[14] = (double)fc[2] / ((double)(g.nz + 1) * g.ny * g.nx);
+            e = hipMemcpyAsync(v, h->d_scratch + (long long)nb * sx::kDiagVals, sizeof v,
+                               hipMemcpyDeviceToHost, h->st);
+        unsigned long long fc[3] = {0, 0, 0};
+        if (e == hipSuccess && h->ks.sensor) {
+            double* Wc = h->W[h->cur];
+            e = sx::launch_ghost_fill(h->kg, h->kgas, Wc, h->st);
+            if (e == hipSuccess)
+                e = sx::launch_sensor_flags(h->kg, h->ks, Wc, h->d_theta, h->d_fx, h->d_fy, h->d_fz,
+                                            h->flag_override, h->d_list, h->d_count, h->st);
+            if (e == hipSuccess) e = sx::launch_count_flags(h->kg, h->d_fx, h->d_fy, h->d_fz, h->d_fcount, h->st);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(fc, h->d_fcount, sizeof fc, hipMemcpyDeviceToHost, h->st);
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+        if (e != hipSuccess) return sx_hip_fail(h, e, "sx_diagnostics");
+        if (h->ks.sensor) {
+            const sx_grid& g = h->grid;
+            v[12] = (double)fc[0] / ((double)g.nz * g.ny * (g.nx + 1));
+            v[13] = (double)fc[1] / ((double)g.nz * (g.ny + 1) * g.nx);
+            v[14] = (double)fc[2] / ((double)(g.nz + 1) * g.ny * g.nx);
+        }
     }
     out->mass = v[0];
     out->momentum[0] = v[1];
@@ -418,7 +435,8 @@ int sx_diagnostics(sx_handle* h, const double* R, sx_diag* out)
     out->weno_fraction[1] = v[13];
     out->weno_fraction[2] = v[14];
     out->volume = v[15];
-    if (v[9] > 0.0 || v[10] > 0.0) return fail(h, SX_ENONFINITE, "sx_diagnostics: non-finite or non-physical state");
+    if (v[9] > 0.0 || v[10] > 0.0)
+        return sx_fail(h, SX_ENONFINITE, "sx_diagnostics: non-finite or non-physical state");
     return SX_OK;
 }
 
@@ -426,12 +444,12 @@ int sx_set_flag_override(sx_handle* h, const unsigned char* fx, const unsigned c
                          const unsigned char* fz)
 {
     if (!h) return SX_EINVAL;
-    if (!h->ks.sensor) return fail(h, SX_ESTATE, "sx_set_flag_override: sensor is off");
+    if (!h->ks.sensor || h->batch) return sx_fail(h, SX_ESTATE, "sx_set_flag_override: sensor is off");
     if (!fx && !fy && !fz) {
         h->flag_override = 0;
         return SX_OK;
     }
-    if (!fx || !fy || !fz) return fail(h, SX_EINVAL, "sx_set_flag_override: need all three arrays");
+    if (!fx || !fy || !fz) return sx_fail(h, SX_EINVAL, "sx_set_flag_override: need all three arrays");
     const sx_grid& g = h->grid;
     hipError_t e = hipMemcpyAsync(h->d_fx, fx, (size_t)g.nz * g.ny * (g.nx + 1), hipMemcpyDefault, h->st);
     if (e == hipSuccess)
@@ -439,7 +457,7 @@ int sx_set_flag_override(sx_handle* h, const unsigned char* fx, const unsigned c
     if (e == hipSuccess)
         e = hipMemcpyAsync(h->d_fz, fz, (size_t)(g.nz + 1) * g.ny * g.nx, hipMemcpyDefault, h->st);
     if (e == hipSuccess) e = hipStreamSynchronize(h->st);
-    if (e != hipSuccess) return hip_fail(h, e, "sx_set_flag_override");
+    if (e != hipSuccess) return sx_hip_fail(h, e, "sx_set_flag_override");
     h->flag_override = 1;
     return SX_OK;
 }
@@ -459,10 +477,10 @@ int sx_timing_read(sx_handle* h, long long* launches, double* total_ms)
         float ms = 0.0f;
         hipError_t e = hipEventSynchronize(p.second);
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, p.first, p.second);
-        if (e != hipSuccess) return hip_fail(h, e, "sx_timing_read");
+        if (e != hipSuccess) return sx_hip_fail(h, e, "sx_timing_read");
         tot += ms;
     }
-    *launches = (long long)h->ev_used.size();
+    *launches = (long long)h->ev_used.size() * h->launches_per_interval;
     *total_ms = tot;
     h->ev_free.insert(h->ev_free.end(), h->ev_used.begin(), h->ev_used.end());
     h->ev_used.clear();

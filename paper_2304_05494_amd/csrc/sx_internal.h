@@ -75,11 +75,42 @@ struct StepCoef {
     int write_prev; // another substep follows
 };
 
+// One block of a batch: its grid, gas and offsets into the state arenas.
+struct BoxDesc {
+    KGrid g;
+    KGas gas;
+    long long woff;   // offset of the box's ghosted state in a state arena
+    long long roff;   // offset of the box's RK register in the register arena
+};
+
+// One work item of the persistent batched kernel.
+struct TileDesc {
+    int box, i0, j0, k0, k1;
+};
+
 // ---- host-side launchers (one per translation unit) --------------------
 hipError_t launch_ghost_fill(const KGrid& g, const KGas& gas, double* W, hipStream_t st);
 hipError_t launch_rhs(const KGrid& g, const KGas& gas, const KScheme& sc, const double* W,
-                      double* out, double* Rprev, const StepCoef* step, unsigned mask,
+                      double* out, double* Rprev, const StepCoef* step, unsigned mask, bool pimg,
                       hipStream_t st);
+// Arguments of one persistent batched launch (one RK3 substep).
+struct BatchLaunch {
+    const double* Wsrc;
+    double* Wdst;
+    double* Rp;
+    const BoxDesc* boxes;
+    const TileDesc* tiles;
+    int ntiles;
+    int* counter;        // work-queue head, reset by the launch itself
+    const double* dt;    // device copy of the time step
+    double gk, zk;       // RK3 coefficients gamma_k, zeta_k of the substep
+    int substep;
+    int nwg;             // workgroups of the persistent grid
+};
+hipError_t launch_batch(const KScheme& sc, int variant, const BatchLaunch& b, hipStream_t st);
+hipError_t launch_set_value(double* p, double v, hipStream_t st);
+int batch_occupancy(const KScheme& sc, int variant);   // resident workgroups per CU
+void batch_tile_shape(const KScheme& sc, int variant, int* tx, int* ty);
 hipError_t launch_diagnostics(const KGrid& g, const KGas& gas, const KScheme& sc,
                               const double* W, const double* R, double* scratch,
                               int nscratch_blocks, hipStream_t st);

@@ -245,29 +245,45 @@ struct PlaneFetch {
     double q[NPT][5];
 };
 
-template <int S, int TX, int TY, int WPE, typename R, bool UPD>
-__global__ void __attribute__((amdgpu_flat_work_group_size(TX * TY, TX * TY), amdgpu_waves_per_eu(WPE)))
-k_rhs_central(const double* __restrict__ W, double* __restrict__ out, double* __restrict__ Rp,
-              KGrid g, KGas gas, StepCoef sc, unsigned mask, int kc)
+// LDS working set of one workgroup (see the file header).
+template <int S, int TX, int TY, typename R>
+struct Smem {
+    static constexpr int NT = TX * TY;
+    static constexpr int HX = TX + 2 * S, HY = TY + 2 * S, HP = HX * HY;
+    static constexpr int Q = 2 * S + 1;
+    R sa[3][HP];                                                    // arrival plane: u, v, w
+    __attribute__((aligned(16))) R so[Layout<R>::PREC * HP];        // output plane records
+    R sH[Layout<R>::SEP_H ? HP : 1];                                // output plane enthalpy
+    R gyl[2][TY][HX];                                               // D_y u, D_y v of plane k
+    __attribute__((aligned(16))) R zring[Q * NT * Layout<R>::ZREC]; // column records
+};
+
+// March one column tile (i0, j0) of one block over planes [k0, k1).
+// PIMG: every direction is periodic and the new state is also written into
+// its periodic ghost images, so the next substep needs no ghost fill.
+template <int S, int TX, int TY, typename R, bool UPD, bool PIMG>
+__device__ __forceinline__ void march(Smem<S, TX, TY, R>& sm, const double* __restrict__ W,
+                                      double* __restrict__ out, double* __restrict__ Rp,
+                                      const KGrid& g, const KGas& gas, const StepCoef& sc,
+                                      unsigned mask_in, int i0, int j0, int k0, int k1)
 {
+    const unsigned mask = UPD ? (unsigned)SX_ALL : mask_in;   // an update always takes every term
     using L = Layout<R>;
     constexpr int NT = TX * TY;
     constexpr int HX = TX + 2 * S, HY = TY + 2 * S, HP = HX * HY;
     constexpr int NPT = (HP + NT - 1) / NT;
     constexpr int Q = 2 * S + 1;
-    __shared__ R sa[3][HP];                                        // arrival plane: u, v, w
-    __shared__ __attribute__((aligned(16))) R so[L::PREC * HP];    // output plane records
-    __shared__ R sH[L::SEP_H ? HP : 1];                            // output plane enthalpy
-    __shared__ R gyl[2][TY][HX];                                   // D_y u, D_y v of plane k
-    __shared__ __attribute__((aligned(16))) R zring[Q * NT * L::ZREC];  // column records
+    auto& sa = sm.sa;
+    R* const so = sm.so;
+    R* const sH = sm.sH;
+    auto& gyl = sm.gyl;
+    R* const zring = sm.zring;
+    (void)HY;
 
     constexpr bool f32 = std::is_same<R, float>::value;
     const double pref = f32 ? gas.pref : 0.0, href = f32 ? gas.href : 0.0;
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
-    const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
-    const int k0 = blockIdx.z * kc;
-    const int k1 = min(k0 + kc, g.nz);
     const int i = i0 + tx, j = j0 + ty;
     const bool active = i < g.nx && j < g.ny;
     const int c = (ty + S) * HX + (tx + S);
@@ -425,6 +441,20 @@ k_rhs_central(const double* __restrict__ W, double* __restrict__ out, double* __
         if (UPD) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) out[v * g.sv + pend_n] = pend_w[v];
+            if constexpr (PIMG) {
+                // periodic images of node (i, j, pend_k) inside the ghost layers
+                const int kk = (int)((pend_n - col) / g.sz);
+                const int ox = i < g.ng ? g.nx : (i >= g.nx - g.ng ? -g.nx : 0);
+                const int oy = j < g.ng ? g.ny : (j >= g.ny - g.ng ? -g.ny : 0);
+                const int oz = kk < g.ng ? g.nz : (kk >= g.nz - g.ng ? -g.nz : 0);
+                for (int c3 = 1; c3 < 8; ++c3) {
+                    const int dx = (c3 & 1) ? ox : 0, dy = (c3 & 2) ? oy : 0, dz = (c3 & 4) ? oz : 0;
+                    if (((c3 & 1) && !ox) || ((c3 & 2) && !oy) || ((c3 & 4) && !oz)) continue;
+                    const long long e = pend_n + dx + (long long)dy * g.sy + (long long)dz * g.sz;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) out[v * g.sv + e] = pend_w[v];
+                }
+            }
             if (sc.write_prev) {
 #pragma unroll
                 for (int v = 0; v < NV; ++v) Rp[v * g.nint + pend_m] = pend[v];
@@ -575,25 +605,85 @@ k_rhs_central(const double* __restrict__ W, double* __restrict__ out, double* __
     flush();
 }
 
+template <int S, int TX, int TY, int WPE, typename R, bool UPD, bool PIMG>
+__global__ void __attribute__((amdgpu_flat_work_group_size(TX * TY, TX * TY), amdgpu_waves_per_eu(WPE)))
+k_rhs_central(const double* __restrict__ W, double* __restrict__ out, double* __restrict__ Rp,
+              KGrid g, KGas gas, StepCoef sc, unsigned mask, int kc)
+{
+    __shared__ Smem<S, TX, TY, R> sm;
+    const int k0 = blockIdx.z * kc;
+    march<S, TX, TY, R, UPD, PIMG>(sm, W, out, Rp, g, gas, sc, mask, blockIdx.x * TX,
+                                   blockIdx.y * TY, k0, min(k0 + kc, g.nz));
+}
+
+// Persistent batched kernel: each workgroup pulls (box, column tile,
+// z-chunk) work items from a device counter until the list is exhausted.
+// The time step is read from device memory, so a captured launch stays
+// valid when dt changes; cg = dt gamma_k and cz = dt zeta_k are formed as on
+// the host path.
+template <int S, int TX, int TY, int WPE, typename R>
+__global__ void __attribute__((amdgpu_flat_work_group_size(TX * TY, TX * TY), amdgpu_waves_per_eu(WPE)))
+k_rhs_batch(const double* __restrict__ Wsrc, double* __restrict__ Wdst, double* __restrict__ Rp,
+            const BoxDesc* __restrict__ boxes, const TileDesc* __restrict__ tiles, int ntiles,
+            int* __restrict__ counter, const double* __restrict__ dtp, double gk, double zk,
+            int substep)
+{
+    __shared__ Smem<S, TX, TY, R> sm;
+    __shared__ int cur;
+    const double dt = *dtp;
+    const StepCoef sc{dt * gk, dt * zk, substep > 0 ? 1 : 0, substep < 2 ? 1 : 0};
+    for (;;) {
+        if (threadIdx.x == 0) cur = atomicAdd(counter, 1);
+        __syncthreads();
+        const int t = cur;
+        __syncthreads();
+        if (t >= ntiles) break;
+        const TileDesc td = tiles[t];
+        const BoxDesc& bd = boxes[td.box];
+        march<S, TX, TY, R, true, true>(sm, Wsrc + bd.woff, Wdst + bd.woff, Rp + bd.roff, bd.g,
+                                        bd.gas, sc, (unsigned)SX_ALL, td.i0, td.j0, td.k0, td.k1);
+        __syncthreads();
+    }
+}
+
+__global__ void k_reset_counter(int* c)
+{
+    if (threadIdx.x == 0) c[0] = 0;
+}
+
+__global__ void k_set_value(double* p, double v)
+{
+    if (threadIdx.x == 0) p[0] = v;
+}
+
 // Tile shapes: FP64 keeps one wave per SIMD (registers), so a 64x4 tile
 // (64x2 for the eighth-order stencil, LDS); FP32 halves registers and LDS,
 // so 64x8 tiles with two waves per SIMD.
+template <typename R, int S>
+struct Tile {
+    static constexpr bool F32 = std::is_same<R, float>::value;
+    static constexpr int TX = 64, TY = F32 ? (S <= 3 ? 8 : 4) : (S <= 3 ? 4 : 2);
+    static constexpr int WPE = F32 ? 2 : 1;
+};
+
 template <int S, typename R>
 static hipError_t launch_rhs_SR(const KGrid& g, const KGas& gas, const double* W, double* out,
-                                double* Rprev, const StepCoef* step, unsigned mask, hipStream_t st)
+                                double* Rprev, const StepCoef* step, unsigned mask, bool pimg,
+                                hipStream_t st)
 {
-    constexpr bool F32 = std::is_same<R, float>::value;
-    constexpr int TX = 64, TY = F32 ? (S <= 3 ? 8 : 4) : (S <= 3 ? 4 : 2);
-    constexpr int WPE = F32 ? 2 : 1;
+    constexpr int TX = Tile<R, S>::TX, TY = Tile<R, S>::TY, WPE = Tile<R, S>::WPE;
     const int kc = g.nz;  // one march over the whole z extent per tile
     dim3 grid((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY, (g.nz + kc - 1) / kc);
-    if (step) {
-        hipLaunchKernelGGL((k_rhs_central<S, TX, TY, WPE, R, true>), grid, dim3(TX * TY), 0, st, W,
-                           out, Rprev, g, gas, *step, (unsigned)SX_ALL, kc);
+    if (step && pimg) {
+        hipLaunchKernelGGL((k_rhs_central<S, TX, TY, WPE, R, true, true>), grid, dim3(TX * TY), 0, st,
+                           W, out, Rprev, g, gas, *step, (unsigned)SX_ALL, kc);
+    } else if (step) {
+        hipLaunchKernelGGL((k_rhs_central<S, TX, TY, WPE, R, true, false>), grid, dim3(TX * TY), 0, st,
+                           W, out, Rprev, g, gas, *step, (unsigned)SX_ALL, kc);
     } else {
         StepCoef none{0.0, 0.0, 0, 0};
-        hipLaunchKernelGGL((k_rhs_central<S, TX, TY, WPE, R, false>), grid, dim3(TX * TY), 0, st, W,
-                           out, Rprev, g, gas, none, mask, kc);
+        hipLaunchKernelGGL((k_rhs_central<S, TX, TY, WPE, R, false, false>), grid, dim3(TX * TY), 0,
+                           st, W, out, Rprev, g, gas, none, mask, kc);
     }
     return hipGetLastError();
 }
@@ -601,24 +691,122 @@ static hipError_t launch_rhs_SR(const KGrid& g, const KGas& gas, const double* W
 template <typename R>
 static hipError_t launch_rhs_R(const KGrid& g, const KGas& gas, const KScheme& sc, const double* W,
                                double* out, double* Rprev, const StepCoef* step, unsigned mask,
-                               hipStream_t st)
+                               bool pimg, hipStream_t st)
 {
     switch (sc.L) {
-    case 1: return launch_rhs_SR<1, R>(g, gas, W, out, Rprev, step, mask, st);
-    case 2: return launch_rhs_SR<2, R>(g, gas, W, out, Rprev, step, mask, st);
-    case 3: return launch_rhs_SR<3, R>(g, gas, W, out, Rprev, step, mask, st);
-    case 4: return launch_rhs_SR<4, R>(g, gas, W, out, Rprev, step, mask, st);
+    case 1: return launch_rhs_SR<1, R>(g, gas, W, out, Rprev, step, mask, pimg, st);
+    case 2: return launch_rhs_SR<2, R>(g, gas, W, out, Rprev, step, mask, pimg, st);
+    case 3: return launch_rhs_SR<3, R>(g, gas, W, out, Rprev, step, mask, pimg, st);
+    case 4: return launch_rhs_SR<4, R>(g, gas, W, out, Rprev, step, mask, pimg, st);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_rhs(const KGrid& g, const KGas& gas, const KScheme& sc, const double* W,
-                      double* out, double* Rprev, const StepCoef* step, unsigned mask,
+                      double* out, double* Rprev, const StepCoef* step, unsigned mask, bool pimg,
                       hipStream_t st)
 {
     if (sc.precision == SX_FP32_FLUX)
-        return launch_rhs_R<float>(g, gas, sc, W, out, Rprev, step, mask, st);
-    return launch_rhs_R<double>(g, gas, sc, W, out, Rprev, step, mask, st);
+        return launch_rhs_R<float>(g, gas, sc, W, out, Rprev, step, mask, pimg, st);
+    return launch_rhs_R<double>(g, gas, sc, W, out, Rprev, step, mask, pimg, st);
+}
+
+// Batched tile shapes: variant 0 is the single-block tile; variant 1 halves
+// the x width and doubles the y height (same thread count), which keeps
+// every lane busy on blocks whose x extent is 32 or 96.
+template <typename R, int S, int V>
+struct BTile {
+    static constexpr int TX = V == 0 ? Tile<R, S>::TX : Tile<R, S>::TX / 2;
+    static constexpr int TY = V == 0 ? Tile<R, S>::TY : Tile<R, S>::TY * 2;
+    static constexpr int WPE = Tile<R, S>::WPE;
+};
+
+template <int S, typename R, int V>
+static hipError_t launch_batch_SRV(const BatchLaunch& b, hipStream_t st)
+{
+    constexpr int TX = BTile<R, S, V>::TX, TY = BTile<R, S, V>::TY, WPE = BTile<R, S, V>::WPE;
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, b.counter);
+    hipLaunchKernelGGL((k_rhs_batch<S, TX, TY, WPE, R>), dim3(b.nwg), dim3(TX * TY), 0, st, b.Wsrc,
+                       b.Wdst, b.Rp, b.boxes, b.tiles, b.ntiles, b.counter, b.dt, b.gk, b.zk,
+                       b.substep);
+    return hipGetLastError();
+}
+
+template <int S, typename R, int V>
+static int occupancy_SRV()
+{
+    constexpr int TX = BTile<R, S, V>::TX, TY = BTile<R, S, V>::TY, WPE = BTile<R, S, V>::WPE;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rhs_batch<S, TX, TY, WPE, R>, TX * TY, 0) !=
+        hipSuccess)
+        return 0;
+    return nb;
+}
+
+template <typename R, int V>
+static hipError_t launch_batch_RV(int L, const BatchLaunch& b, hipStream_t st)
+{
+    switch (L) {
+    case 1: return launch_batch_SRV<1, R, V>(b, st);
+    case 2: return launch_batch_SRV<2, R, V>(b, st);
+    case 3: return launch_batch_SRV<3, R, V>(b, st);
+    case 4: return launch_batch_SRV<4, R, V>(b, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename R, int V>
+static int occupancy_RV(int L)
+{
+    switch (L) {
+    case 1: return occupancy_SRV<1, R, V>();
+    case 2: return occupancy_SRV<2, R, V>();
+    case 3: return occupancy_SRV<3, R, V>();
+    case 4: return occupancy_SRV<4, R, V>();
+    default: return 0;
+    }
+}
+
+hipError_t launch_batch(const KScheme& sc, int variant, const BatchLaunch& b, hipStream_t st)
+{
+    const bool f32 = sc.precision == SX_FP32_FLUX;
+    if (variant == 0)
+        return f32 ? launch_batch_RV<float, 0>(sc.L, b, st) : launch_batch_RV<double, 0>(sc.L, b, st);
+    if (variant == 1)
+        return f32 ? launch_batch_RV<float, 1>(sc.L, b, st) : launch_batch_RV<double, 1>(sc.L, b, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_set_value(double* p, double v, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_set_value, dim3(1), dim3(64), 0, st, p, v);
+    return hipGetLastError();
+}
+
+int batch_occupancy(const KScheme& sc, int variant)
+{
+    const bool f32 = sc.precision == SX_FP32_FLUX;
+    if (variant == 0) return f32 ? occupancy_RV<float, 0>(sc.L) : occupancy_RV<double, 0>(sc.L);
+    if (variant == 1) return f32 ? occupancy_RV<float, 1>(sc.L) : occupancy_RV<double, 1>(sc.L);
+    return 0;
+}
+
+template <typename R>
+static void tile_shape_R(int L, int variant, int* tx, int* ty)
+{
+    const bool v1 = variant == 1;
+    switch (L) {
+    case 1: *tx = v1 ? BTile<R, 1, 1>::TX : BTile<R, 1, 0>::TX; *ty = v1 ? BTile<R, 1, 1>::TY : BTile<R, 1, 0>::TY; break;
+    case 2: *tx = v1 ? BTile<R, 2, 1>::TX : BTile<R, 2, 0>::TX; *ty = v1 ? BTile<R, 2, 1>::TY : BTile<R, 2, 0>::TY; break;
+    case 3: *tx = v1 ? BTile<R, 3, 1>::TX : BTile<R, 3, 0>::TX; *ty = v1 ? BTile<R, 3, 1>::TY : BTile<R, 3, 0>::TY; break;
+    default: *tx = v1 ? BTile<R, 4, 1>::TX : BTile<R, 4, 0>::TX; *ty = v1 ? BTile<R, 4, 1>::TY : BTile<R, 4, 0>::TY; break;
+    }
+}
+
+void batch_tile_shape(const KScheme& sc, int variant, int* tx, int* ty)
+{
+    if (sc.precision == SX_FP32_FLUX) tile_shape_R<float>(sc.L, variant, tx, ty);
+    else tile_shape_R<double>(sc.L, variant, tx, ty);
 }
 
 }  // namespace sx

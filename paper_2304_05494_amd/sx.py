@@ -69,10 +69,16 @@ class sx_diag(ctypes.Structure):
                          self.residual_rhou, *self.weno_fraction, self.volume])
 
 
+class sx_tiling(ctypes.Structure):
+    _fields_ = [("tile_x", ctypes.c_int), ("tile_y", ctypes.c_int), ("zchunk", ctypes.c_int),
+                ("workgroups", ctypes.c_int), ("work_items", ctypes.c_int),
+                ("ms_per_substep", ctypes.c_double)]
+
+
 EXPORTS = ["sx_init", "sx_finalize", "sx_get_layout", "sx_bind", "sx_current", "sx_fill_ghosts",
            "sx_rhs", "sx_rk3_step", "sx_compute_dt", "sx_diagnostics", "sx_set_flag_override",
-           "sx_timing_enable",
-           "sx_timing_read", "sx_last_error"]
+           "sx_timing_enable", "sx_timing_read", "sx_init_batch", "sx_get_box", "sx_set_tiling",
+           "sx_get_tiling", "sx_autotune", "sx_set_graph", "sx_last_error"]
 
 _lib = None
 
@@ -103,6 +109,14 @@ def load() -> ctypes.CDLL:
     L.sx_set_flag_override.argtypes = [H, dp, dp, dp]
     L.sx_timing_enable.argtypes = [H, ctypes.c_int]
     L.sx_timing_read.argtypes = [H, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double)]
+    L.sx_init_batch.argtypes = [ctypes.c_int, ctypes.POINTER(sx_grid), ctypes.POINTER(sx_gas),
+                                ctypes.POINTER(sx_scheme), ctypes.POINTER(H)]
+    L.sx_get_box.argtypes = [H, ctypes.c_int, ctypes.POINTER(sx_layout),
+                             ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]
+    L.sx_set_tiling.argtypes = [H, ctypes.POINTER(sx_tiling)]
+    L.sx_get_tiling.argtypes = [H, ctypes.POINTER(sx_tiling)]
+    L.sx_autotune.argtypes = [H, ctypes.c_char_p, ctypes.POINTER(sx_tiling)]
+    L.sx_set_graph.argtypes = [H, ctypes.c_int]
     L.sx_last_error.argtypes = [H]
     L.sx_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -254,3 +268,98 @@ class Handle:
             self._check(rc)
         d.status = rc
         return d
+
+
+class BatchHandle(Handle):
+    """Owns a batch sx_handle (many periodic blocks, one scheme) and its
+    state / register arenas."""
+
+    def __init__(self, cases, precision: int = SX_FP64):
+        import torch
+        self.lib = load()
+        self.cases = list(cases)
+        n = len(self.cases)
+        grids = (sx_grid * n)()
+        gases = (sx_gas * n)()
+        sc = None
+        for b, c in enumerate(self.cases):
+            g, gas, s = make_structs(c, precision)
+            grids[b] = g
+            gases[b] = gas
+            sc = sc or s
+        h = ctypes.c_void_p()
+        rc = self.lib.sx_init_batch(n, grids, gases, ctypes.byref(sc), ctypes.byref(h))
+        if rc != SX_OK:
+            raise SxError(rc, "sx_init_batch rejected the description")
+        self.h = h
+        lay = sx_layout()
+        self._check(self.lib.sx_get_layout(h, ctypes.byref(lay)))
+        self.layout = lay
+        self.boxes = []
+        for b in range(n):
+            bl = sx_layout()
+            wo, ro = ctypes.c_longlong(), ctypes.c_longlong()
+            self._check(self.lib.sx_get_box(h, b, ctypes.byref(bl), ctypes.byref(wo), ctypes.byref(ro)))
+            self.boxes.append((bl, wo.value, ro.value))
+        self.ng, self.ox = lay.ng, lay.ox
+        self.W = None
+        self.torch = torch
+
+    def box_view(self, A, b):
+        """View of block b's ghosted state [5, pz, py, px] inside a state arena."""
+        bl, wo, _ = self.boxes[b]
+        return A[wo:wo + bl.elems].view(5, bl.pz, bl.py, bl.px)
+
+    def box_rhs_view(self, R, b):
+        c = self.cases[b]
+        _, _, ro = self.boxes[b]
+        n = c.nx * c.ny * c.nz
+        return R[ro:ro + 5 * n].view(5, c.nz, c.ny, c.nx)
+
+    def to_arena(self, fields):
+        """Neutral ghosted arrays (one per block) -> a float64 device state arena."""
+        out = np.zeros(self.layout.elems)
+        g = self.ng
+        for b, (Wn, c) in enumerate(zip(fields, self.cases)):
+            bl, wo, _ = self.boxes[b]
+            v = out[wo:wo + bl.elems].reshape(5, bl.pz, bl.py, bl.px)
+            v[:, :, :, bl.ox - g:bl.ox + c.nx + g] = Wn
+        return self.torch.from_numpy(out).to("cuda")
+
+    def box_interior(self, A, b) -> np.ndarray:
+        c = self.cases[b]
+        bl, _, _ = self.boxes[b]
+        g = self.ng
+        a = self.box_view(A, b).detach().cpu().numpy()
+        return np.ascontiguousarray(a[:, g:g + c.nz, g:g + c.ny, bl.ox:bl.ox + c.nx])
+
+    def sx_bind(self, W0, W1=None, Rprev=None, stream=None):
+        torch = self.torch
+        if Rprev is None:
+            Rprev = torch.empty(5 * self.layout.interior, dtype=torch.float64, device=W0.device)
+        super().sx_bind(W0, W1, Rprev, stream)
+
+    def sx_rhs(self, W, R=None, mask: int = SX_ALL):
+        if R is None:
+            R = self.torch.zeros(5 * self.layout.interior, dtype=self.torch.float64, device=W.device)
+        self._check(self.lib.sx_rhs(self.h, _ptr(W), _ptr(R), mask))
+        return R
+
+    def sx_set_tiling(self, tile_x: int, zchunk: int, workgroups: int = 0):
+        t = sx_tiling(tile_x, 0, zchunk, workgroups, 0, 0.0)
+        self._check(self.lib.sx_set_tiling(self.h, ctypes.byref(t)))
+        return self.sx_get_tiling()
+
+    def sx_get_tiling(self) -> sx_tiling:
+        t = sx_tiling()
+        self._check(self.lib.sx_get_tiling(self.h, ctypes.byref(t)))
+        return t
+
+    def sx_autotune(self, cache_path=None) -> sx_tiling:
+        t = sx_tiling()
+        p = None if cache_path is None else str(cache_path).encode()
+        self._check(self.lib.sx_autotune(self.h, p, ctypes.byref(t)))
+        return t
+
+    def sx_set_graph(self, enable: bool = True):
+        self._check(self.lib.sx_set_graph(self.h, int(enable)))

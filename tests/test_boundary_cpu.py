@@ -32,7 +32,7 @@ def test_struct_layouts_match_the_c_header(tmp_path):
     """Compile the header with gcc and compare every field offset and struct
     size with the ctypes mirrors used by the binding."""
     import subprocess
-    structs = [sx.sx_grid, sx.sx_gas, sx.sx_scheme, sx.sx_layout, sx.sx_diag]
+    structs = [sx.sx_grid, sx.sx_gas, sx.sx_scheme, sx.sx_layout, sx.sx_diag, sx.sx_tiling]
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sx.h"', 'int main(void){']
     for st in structs:
         n = st.__name__
@@ -97,3 +97,44 @@ def test_null_arguments():
     assert L.sx_rk3_step(None, ctypes.c_double(1.0)) == sx.SX_EINVAL
     assert L.sx_last_error(None) == b"null handle"
     L.sx_finalize(None)
+
+
+def _init_batch(cases, **patch):
+    L = sx.load()
+    n = len(cases)
+    grids, gases = (sx.sx_grid * n)(), (sx.sx_gas * n)()
+    sc = None
+    for b, c in enumerate(cases):
+        g, gas, s = sx.make_structs(c)
+        for k, v in patch.items():
+            if hasattr(g, k):
+                setattr(g, k, v)
+            if hasattr(s, k):
+                setattr(s, k, v)
+        grids[b], gases[b] = g, gas
+        sc = sc or s
+    h = ctypes.c_void_p()
+    rc = L.sx_init_batch(n, grids, gases, ctypes.byref(sc), ctypes.byref(h))
+    return rc, h
+
+
+def test_batch_rejections_without_device():
+    cases = [inputs.tgv_case(16), inputs.tgv_case(24)]
+    L = sx.load()
+    h = ctypes.c_void_p()
+    g, gas, sc = sx.make_structs(cases[0])
+    assert L.sx_init_batch(0, ctypes.byref(g), ctypes.byref(gas), ctypes.byref(sc), ctypes.byref(h)) == sx.SX_EINVAL
+    assert L.sx_init_batch(1, None, None, None, ctypes.byref(h)) == sx.SX_EINVAL
+    # the batched form is the central path on periodic blocks
+    assert _init_batch(cases, sensor=1)[0] == sx.SX_EUNSUPPORTED
+    ch = inputs.channel_case(32, 16, 8)
+    assert _init_batch([ch])[0] == sx.SX_EUNSUPPORTED
+    assert _init_batch(cases, central_order=5)[0] == sx.SX_EINVAL
+    # blocks narrower than twice the ghost width cannot hold periodic images
+    small = inputs.Case(**{**inputs.tgv_case(16).__dict__, "nz": 5})
+    assert _init_batch([small])[0] == sx.SX_EUNSUPPORTED
+    t = sx.sx_tiling()
+    assert L.sx_get_box(None, 0, None, None, None) == sx.SX_EINVAL
+    assert L.sx_set_tiling(None, ctypes.byref(t)) == sx.SX_EINVAL
+    assert L.sx_autotune(None, None, None) == sx.SX_EINVAL
+    assert L.sx_set_graph(None, 1) == sx.SX_EINVAL
