@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain device copy of 2 GiB (counter calibration)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form legs")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the TGV, shock/boundary-layer and FP32-error legs")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON autotune cache of the batched form (default: tune afresh)")
     return ap.parse_args()
@@ -97,6 +99,106 @@ def cpu_baseline(case, Wn, dt, steps):
             "cores": O.num_threads(), "kind": "oracle",
             "sample": f"{steps} RK3 step(s) of the full {case.nx}x{case.ny}x{case.nz} workload "
                       f"({el:.1f} s, OpenMP over z-planes)"}
+
+
+def time_steps(h, dt, steps, warmup):
+    """Wall time per RK3 step (HIP events on the bound stream) and the
+    per-launch time of the fused RHS/update kernel."""
+    import torch
+    for _ in range(warmup):
+        h.sx_rk3_step(dt)
+    torch.cuda.synchronize()
+    h.sx_timing_enable(True)
+    h.sx_timing_read()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        h.sx_rk3_step(dt)
+    stop.record()
+    torch.cuda.synchronize()
+    n, kms = h.sx_timing_read()
+    h.sx_timing_enable(False)
+    return start.elapsed_time(stop) / steps, kms / n
+
+
+def bench_tgv(args):
+    """Taylor-Green vortex 32^3 (the small correctness case): launch-bound,
+    rate reported without a roofline claim."""
+    import numpy as np
+    from paper_2304_05494_amd import inputs, sx
+    case = inputs.tgv_case(32)
+    h = sx.Handle(case)
+    h.sx_bind(h.to_layout(np.ascontiguousarray(inputs.fields(case))))
+    dt = h.sx_compute_dt(case.cfl)
+    ms, _ = time_steps(h, dt, 10, args.warmup)
+    return {"value": case.points / (ms * 1e-3), "ms_per_step": ms, "steps": 10,
+            "workload": "Taylor-Green vortex 32^3, M0 0.1, Re 1600, C6 + V6, FP64"}
+
+
+def bench_shock_bl(args):
+    """Shock / boundary-layer block 1024x256x128 with the Ducros sensor and
+    WENO-5 characteristic fluxes on flagged faces (FP64 and FP32-flux)."""
+    import numpy as np
+    import torch
+    from paper_2304_05494_amd import inputs, sx
+    case = inputs.shock_bl_case()
+    Wn = np.ascontiguousarray(inputs.fields(case))
+    out = {"workload": "shock/boundary-layer block 1024x256x128: Mach 2 flat-plate boundary "
+                       "layer + 8 deg oblique shock, W5 where the Ducros sensor exceeds 0.5, "
+                       "C6 + V6 elsewhere",
+           "points": case.points}
+    dt = None
+    ms64 = None
+    for prec, name in ((sx.SX_FP64, "fp64"), (sx.SX_FP32_FLUX, "fp32_flux")):
+        h = sx.Handle(case, prec)
+        h.sx_bind(h.to_layout(Wn))
+        if dt is None:
+            dt = h.sx_compute_dt(case.cfl)
+            d = h.sx_diagnostics()
+            out["weno_face_fraction"] = list(d.weno_fraction)
+        ms, kms = time_steps(h, dt, args.steps, args.warmup)
+        d = h.sx_diagnostics()
+        out[name] = {"value": case.points / (ms * 1e-3), "ms_per_step": ms,
+                     "central_kernel_ms": kms, "state_ok": d.status == sx.SX_OK}
+        if ms64 is None:
+            ms64 = ms
+        else:
+            out[name]["speedup_vs_fp64"] = ms64 / ms
+        del h
+        torch.cuda.empty_cache()
+    return out
+
+
+def fp32_error(case, Wn, dt, steps):
+    """Per-variable relative L2 and Linf difference between the FP32-flux
+    form and the FP64 path after `steps` RK3 steps from the same state."""
+    import numpy as np
+    import torch
+    from paper_2304_05494_amd import sx
+    res = []
+    for prec in (sx.SX_FP64, sx.SX_FP32_FLUX):
+        h = sx.Handle(case, prec)
+        h.sx_bind(h.to_layout(Wn))
+        for _ in range(steps):
+            h.sx_rk3_step(dt)
+        torch.cuda.synchronize()
+        res.append(h.interior(h.state))
+        del h
+        torch.cuda.empty_cache()
+    a, b = res[1], res[0]
+    names = ["rho", "rho_u", "rho_v", "rho_w", "rho_E"]
+    out = {}
+    for v, nm in enumerate(names):
+        d = a[v] - b[v]
+        ref2 = float(np.sqrt(np.mean(b[v] ** 2)))
+        refi = float(np.abs(b[v]).max())
+        # momentum components are scaled by the momentum magnitude
+        if 1 <= v <= 3:
+            mag = np.sqrt(b[1] ** 2 + b[2] ** 2 + b[3] ** 2)
+            ref2, refi = float(np.sqrt(np.mean(mag ** 2))), float(mag.max())
+        out[nm] = {"l2_rel": float(np.sqrt(np.mean(d ** 2))) / ref2,
+                   "linf_rel": float(np.abs(d).max()) / refi}
+    return out
 
 
 def bench_batch(args, precision, fields=None):
@@ -258,6 +360,10 @@ def main():
                                        "128x64x64; TGV or decaying turbulence; Mach 0.1-0.5), "
                                        "C6 + V6, one graph-replayed persistent launch per substep",
                            "fp64": b64, "fp32_flux": b32}
+    if not args.no_legs:
+        line["tgv32"] = bench_tgv(args)
+        line["shock_bl"] = bench_shock_bl(args)
+        line["fp32_flux"]["error_vs_fp64_after_100_steps"] = fp32_error(case, Wn, dt, 100)
     if not args.no_cpu_baseline:
         del h, W0
         torch.cuda.empty_cache()
