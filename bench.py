@@ -2,15 +2,20 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
-Workload: the channel-like block 512x256x256 in FP64 (periodic x/z,
-isothermal tanh-stretched walls in y, bulk Mach 1.5, Re_b 6000, sixth-order
-central split-form convection + sixth-order Laplacian viscous terms), seeded
-synthetic input, inputs resident in HBM before the timed region. One step =
-one full RK3 step (three fused RHS/update substeps + ghost fills).
+Headline workload: the channel-like block 512x256x256 in FP64 (periodic
+x/z, isothermal tanh-stretched walls in y, bulk Mach 1.5, Re_b 6000,
+sixth-order central split-form convection + sixth-order Laplacian viscous
+terms), seeded synthetic input, inputs resident in HBM before the timed
+region. One step = one full RK3 step (three fused RHS/update substeps +
+ghost fills).
 
 Prints one JSON line: throughput (grid-point updates per second per RK3
 step), the roofline of the dominant kernel (the fused RHS/update kernel,
-timed live with HIP events on its stream) and the CPU oracle baseline.
+timed live with HIP events on its stream) and the CPU oracle baseline,
+plus side legs: the same block in the FP32-flux form (and its per-variable
+difference from the FP64 path after 100 steps), the Taylor-Green vortex
+32^3, the shock/boundary-layer block 1024x256x128 with the sensor and WENO-5,
+and the 48-block batched form in FP64 and FP32-flux.
 """
 from __future__ import annotations
 

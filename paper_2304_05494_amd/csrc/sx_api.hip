@@ -43,6 +43,7 @@ double y_node(const sx_grid& g, int j)
 
 bool valid_order(int o) { return o == 2 || o == 4 || o == 6 || o == 8; }
 
+
 }  // namespace
 
 // Event pair around launches on the bound stream (timing mode).
@@ -105,6 +106,7 @@ int sx_validate(const sx_grid& g, const sx_gas& gas, const sx_scheme& s, int* ng
     if (!(gas.gamma > 1.0) || !(gas.mach > 0.0) || !(gas.reynolds > 0.0) || !(gas.prandtl > 0.0))
         return SX_EINVAL;
     if (!(g.lx > 0.0) || !(g.ly > 0.0) || !(g.lz > 0.0)) return SX_EINVAL;
+
     if (g.ymap < SX_Y_UNIFORM || g.ymap > SX_Y_TANH1) return SX_EINVAL;
     if (g.ymap != SX_Y_UNIFORM && !(g.beta > 0.0)) return SX_EINVAL;
     const int L = s.central_order / 2, Lv = s.visc_order / 2, r = (s.weno_order + 1) / 2;
@@ -155,6 +157,7 @@ void sx_fill_kernel_params(const sx_grid& g, const sx_gas& gas, const sx_scheme&
     kgas->igM2 = 1.0 / kgas->gM2;
     kgas->cp = 1.0 / (kgas->gm1 * gas.mach * gas.mach);
     kgas->s = gas.visc_exp;
+    kgas->sf = (float)gas.visc_exp;
     kgas->ire = 1.0 / gas.reynolds;
     kgas->ipr = 1.0 / gas.prandtl;
     kgas->t_wall = gas.t_wall;

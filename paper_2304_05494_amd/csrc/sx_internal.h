@@ -30,6 +30,7 @@ struct KGas {
     double igM2;                // 1/(gamma M^2)
     double cp;                  // 1/((gamma-1) M^2)
     double s;                   // viscosity exponent
+    float sf;                   // s in FP32
     double ire;                 // 1/Re
     double ipr;                 // 1/Pr
     double t_wall;

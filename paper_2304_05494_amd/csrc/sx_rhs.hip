@@ -59,12 +59,17 @@ __device__ __forceinline__ R d1(const R (&f)[2 * S + 1])
     return s;
 }
 
+// Viscosity law T^s: FP64 through exp(s log T); FP32 through the hardware
+// base-2 logarithm and exponential.
 template <typename R>
-__device__ __forceinline__ R powr(R x, R s);
+__device__ __forceinline__ R visc_pow(R T, const KGas& gas);
 template <>
-__device__ __forceinline__ double powr<double>(double x, double s) { return exp(s * log(x)); }
+__device__ __forceinline__ double visc_pow<double>(double T, const KGas& gas) { return exp(gas.s * log(T)); }
 template <>
-__device__ __forceinline__ float powr<float>(float x, float s) { return expf(s * logf(x)); }
+__device__ __forceinline__ float visc_pow<float>(float T, const KGas& gas)
+{
+    return __builtin_amdgcn_exp2f(gas.sf * __builtin_amdgcn_logf(T));
+}
 
 template <typename R>
 __device__ __forceinline__ R rcpr(R x);
@@ -514,7 +519,7 @@ __device__ __forceinline__ void march(Smem<S, TX, TY, R>& sm, const double* __re
             const R uc = Cz.u, vc = Cz.v, wc_ = Cz.w, Tc = Cz.T;
             R mu = 0, kcd = 0, smt = 0;
             if (visc) {
-                mu = powr<R>(Tc, R(gas.s)) * R(gas.ire);
+                mu = visc_pow<R>(Tc, gas) * R(gas.ire);
                 kcd = mu * R(gas.cp * gas.ipr);
                 smt = R(gas.s) * rcpr<R>(Tc);
             }

@@ -28,6 +28,15 @@ def _cases():
                          central_order=4, visc_order=4, mach=0.3, reynolds=100.0))
     c.append(inputs.Case(name="tgv-c8", nx=66, ny=10, nz=9, lx=two_pi, ly=two_pi, lz=two_pi,
                          central_order=8, visc_order=8, mach=0.3, reynolds=100.0))
+    # degenerate periodic blocks: n between g and 2g (ghosts filled by a
+    # launch every substep), n = 2g exactly and odd sizes (periodic images
+    # written by the update itself)
+    c.append(inputs.Case(name="tgv-c6-min4", nx=4, ny=5, nz=4, lx=two_pi, ly=two_pi, lz=two_pi,
+                         mach=0.3, reynolds=100.0))
+    c.append(inputs.Case(name="tgv-c6-img6", nx=6, ny=6, nz=6, lx=two_pi, ly=two_pi, lz=two_pi,
+                         mach=0.3, reynolds=100.0))
+    c.append(inputs.Case(name="tgv-c6-odd", nx=7, ny=9, nz=11, lx=two_pi, ly=two_pi, lz=two_pi,
+                         mach=0.3, reynolds=100.0))
     c.append(inputs.Case(name="channel-uniform", nx=40, ny=24, nz=8, lx=2.0, ly=2.0, lz=1.0,
                          y0=-1.0 + 1.0 / 24, bc=(0, 0, 1, 1, 0, 0), mach=0.5, reynolds=300.0,
                          seed=7, t_wall=1.0))
@@ -96,7 +105,13 @@ def test_rhs_term_parity(case, mask):
     assert_rhs_close(got, ref, 1e-11)
 
 
-@pytest.mark.parametrize("case,nsteps", [(CASES[0], 10), (CASES[1], 10), (CASES[4], 4), (CASES[5], 6)],
+BY_NAME = {c.name: c for c in CASES}
+
+
+@pytest.mark.parametrize("case,nsteps", [(CASES[0], 10), (CASES[1], 10), (BY_NAME["tgv-c8"], 4),
+                                         (BY_NAME["channel-uniform"], 6),
+                                         (BY_NAME["tgv-c6-min4"], 5), (BY_NAME["tgv-c6-img6"], 5),
+                                         (BY_NAME["tgv-c6-odd"], 5)],
                          ids=lambda x: getattr(x, "name", str(x)))
 def test_rk3_steps_parity(case, nsteps):
     h, Wn, W = _setup(case)
@@ -204,3 +219,65 @@ def test_full_size_channel_rhs_sampled_points():
     del R, W
     ref = oracle_for(case).rhs_points(Wn, pts)
     assert_rhs_close(got.T[:, :, None, None], ref.T[:, :, None, None], 1e-11)
+
+
+def sampled_rk3_step(o, Wn, pts, dt, reach):
+    """One oracle RK3 step evaluated only where it influences the nodes
+    `pts` (interior nodes at least 3*reach from every boundary): the RHS of
+    substep s is taken on boxes of radius (3-s)*reach around the samples,
+    with `reach` the radius of dependence of one RHS evaluation."""
+    gk = (8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0)
+    zk = (0.0, -17.0 / 60.0, -5.0 / 12.0)
+    g = o.ng
+
+    def box(rad):
+        s = set()
+        r = np.arange(-rad, rad + 1)
+        for p in pts:
+            X, Y, Z = np.meshgrid(p[0] + r, p[1] + r, p[2] + r, indexing="ij")
+            s.update(zip(X.ravel().tolist(), Y.ravel().tolist(), Z.ravel().tolist()))
+        return np.array(sorted(s), dtype=np.int32)
+
+    W = Wn.copy()
+    Rprev = {}
+    for s in range(3):
+        b = box((2 - s) * reach)
+        R = o.rhs_points(W, b)
+        key = [tuple(x) for x in b.tolist()]
+        Wnew = W.copy()
+        for n, (i, j, k) in enumerate(key):
+            prev = Rprev.get((i, j, k), np.zeros(5))
+            Wnew[:, k + g, j + g, i + g] = (W[:, k + g, j + g, i + g] + dt * gk[s] * R[n]
+                                            + dt * zk[s] * prev)
+        Rprev = {key[n]: R[n] for n in range(len(key))}
+        W = Wnew
+    return np.stack([W[:, p[2] + g, p[1] + g, p[0] + g] for p in pts])
+
+
+def test_full_size_channel_rk3_step_sampled_points():
+    """One RK3 step of the 512x256x256 channel block through sx_rk3_step
+    (the fused update kernel the bench times) against the oracle's step at
+    sampled interior nodes."""
+    case = inputs.channel_case()
+    h = sx.Handle(case)
+    Wn = np.ascontiguousarray(inputs.fields(case))
+    h.sx_bind(h.to_layout(Wn))
+    dt = h.sx_compute_dt(case.cfl)
+    h.sx_rk3_step(dt)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(12)
+    reach = 3
+    lo = 3 * reach
+    pts = np.stack([rng.integers(lo, n - lo, 6) for n in (case.nx, case.ny, case.nz)], axis=1)
+    pts = np.concatenate([pts, [[63, 3 + lo, 100], [64, 4 + lo, 101]]]).astype(np.int32)
+    st = h.state
+    got = np.stack([st[:, p[2] + h.ng, p[1] + h.ng, p[0] + h.ox].cpu().numpy() for p in pts])
+    del st, h
+    torch.cuda.empty_cache()
+    o = oracle_for(case)
+    ref = sampled_rk3_step(o, Wn, pts, dt, reach)
+    scale = np.abs(ref).max(axis=0)
+    scale[1:4] = np.sqrt((ref[:, 1:4] ** 2).sum(axis=1)).max()
+    err = np.abs(got - ref).max(axis=0) / scale
+    assert np.all(err < 1e-12), err
+    assert np.abs(ref - np.stack([Wn[:, p[2] + 3, p[1] + 3, p[0] + 3] for p in pts])).max() > 0

@@ -117,3 +117,30 @@ def test_hybrid_determinism():
         torch.cuda.synchronize()
         out.append(h.state.clone())
     assert torch.equal(out[0], out[1])
+
+
+def test_full_size_shock_boundary_layer_rhs_sampled_points():
+    """The 1024x256x128 shock/boundary-layer block with WENO-5 where the
+    sensor flags faces: sx_rhs on the GPU against the oracle at sampled
+    nodes, half of them next to flagged faces."""
+    case = inputs.shock_bl_case()
+    Wn = np.ascontiguousarray(inputs.fields(case))
+    print("fields ready", flush=True)
+    h = sx.Handle(case)
+    W = h.to_layout(Wn)
+    h.sx_bind(W)
+    R = h.sx_rhs(W)
+    torch.cuda.synchronize()
+    o = oracle_for(case)
+    fx, fy, fz = o.face_flags(Wn.copy())
+    rng = np.random.default_rng(21)
+    flagged = np.argwhere(fx[:, :, :-1] | fy[:, :-1, :] | fz[:-1, :, :])   # (k, j, i): face below node
+    near = flagged[rng.choice(len(flagged), 200, replace=False)][:, ::-1]
+    rand = np.stack([rng.integers(0, n, 200) for n in (case.nx, case.ny, case.nz)], axis=1)
+    edge = np.array([[i, j, k] for i in (0, 1023) for j in (0, 255) for k in (0, 127)])
+    pts = np.concatenate([near, rand, edge]).astype(np.int32)
+    got = R[:, pts[:, 2], pts[:, 1], pts[:, 0]].cpu().numpy().T
+    del R, W, h
+    torch.cuda.empty_cache()
+    ref = o.rhs_points(Wn, pts)
+    assert_rhs_close(got.T[:, :, None, None], ref.T[:, :, None, None], 1e-11)
