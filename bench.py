@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle timing (profiling runs)")
-    ap.add_argument("--cpu-sample-steps", type=int, default=1)
+    ap.add_argument("--cpu-sample-steps", type=int, default=4)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain device copy of 2 GiB (counter calibration)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form legs")
@@ -293,7 +293,7 @@ def main():
     avg_launch_s = kern_ms / launches * 1e-3
     alg_bytes_launch = ALG_BYTES_PER_POINT_STEP / SUBSTEPS * case.points
     achieved = alg_bytes_launch / avg_launch_s / 1e9
-    kernel = "k_rhs_central<3, 64, 4, 1, double, true, false>"
+    kernel = "k_rhs_central<3, 32, 8, 1, double, true, false>"
     traffic = load_traffic(kernel)
     line = {
         "metric": "grid-point updates/s per RK3 step (FP64 vs FP32-flux) + % HBM roofline",

@@ -226,12 +226,17 @@ int sx_init(const sx_grid* grid, const sx_gas* gas, const sx_scheme* scheme, sx_
         e = hipMalloc(&h->d_scratch, sizeof(double) * (sx::kReduceBlocks + 1) * sx::kDiagVals);
     if (e == hipSuccess && s.sensor) {
         const long long ni = h->lay.interior;
-        e = hipMalloc(&h->d_theta, sizeof(double) * ni);
-        if (e == hipSuccess) e = hipMalloc(&h->d_fx, (size_t)g.nz * g.ny * (g.nx + 1));
-        if (e == hipSuccess) e = hipMalloc(&h->d_fy, (size_t)g.nz * (g.ny + 1) * g.nx);
-        if (e == hipSuccess) e = hipMalloc(&h->d_fz, (size_t)(g.nz + 1) * g.ny * g.nx);
-        if (e == hipSuccess) e = hipMalloc(&h->d_list, sizeof(int) * ni);
-        if (e == hipSuccess) e = hipMalloc(&h->d_count, sizeof(int));
+        const long long nf[3] = {(long long)g.nz * g.ny * (g.nx + 1), (long long)g.nz * (g.ny + 1) * g.nx,
+                                 (long long)(g.nz + 1) * g.ny * g.nx};
+        sx::WenoBufs& b = h->wb;
+        e = hipMalloc(&b.theta, sizeof(double) * ni);
+        for (int d = 0; d < 3 && e == hipSuccess; ++d) {
+            e = hipMalloc(&b.f[d], (size_t)nf[d]);
+            if (e == hipSuccess) e = hipMalloc(&b.flist[d], sizeof(int) * nf[d]);
+            if (e == hipSuccess) e = hipMalloc(&b.dF[d], sizeof(double) * sx::NV * nf[d]);
+        }
+        if (e == hipSuccess) e = hipMalloc(&b.nlist, sizeof(int) * ni);
+        if (e == hipSuccess) e = hipMalloc(&b.counts, sizeof(int) * 4);
         if (e == hipSuccess) e = hipMalloc(&h->d_fcount, sizeof(unsigned long long) * 3);
     }
     if (e != hipSuccess) {
@@ -245,9 +250,11 @@ int sx_init(const sx_grid* grid, const sx_gas* gas, const sx_scheme* scheme, sx_
 void sx_finalize(sx_handle* h)
 {
     if (!h) return;
-    for (void* p : {(void*)h->d_metrics, (void*)h->d_scratch, (void*)h->d_theta, (void*)h->d_fx,
-                    (void*)h->d_fy, (void*)h->d_fz, (void*)h->d_list, (void*)h->d_count,
-                    (void*)h->d_fcount})
+    const sx::WenoBufs& b = h->wb;
+    for (void* p : {(void*)h->d_metrics, (void*)h->d_scratch, (void*)b.theta, (void*)b.f[0],
+                    (void*)b.f[1], (void*)b.f[2], (void*)b.flist[0], (void*)b.flist[1],
+                    (void*)b.flist[2], (void*)b.dF[0], (void*)b.dF[1], (void*)b.dF[2],
+                    (void*)b.nlist, (void*)b.counts, (void*)h->d_fcount})
         if (p) (void)hipFree(p);
     for (auto* v : {&h->ev_used, &h->ev_free})
         for (auto& p : *v) {
@@ -323,11 +330,9 @@ int sx_rhs(sx_handle* h, double* W, double* R, unsigned term_mask)
     if (e == hipSuccess)
         e = sx::launch_rhs(h->kg, h->kgas, h->ks, W, R, nullptr, nullptr, term_mask, false, h->st);
     if (e == hipSuccess && h->ks.sensor && (term_mask & (SX_CONV_X | SX_CONV_Y | SX_CONV_Z))) {
-        e = sx::launch_sensor_flags(h->kg, h->ks, W, h->d_theta, h->d_fx, h->d_fy, h->d_fz,
-                                    h->flag_override, h->d_list, h->d_count, h->st);
+        e = sx::launch_sensor_flags(h->kg, h->ks, W, h->wb, h->flag_override, h->st);
         if (e == hipSuccess)
-            e = sx::launch_weno(h->kg, h->kgas, h->ks, term_mask, W, h->d_fx, h->d_fy, h->d_fz,
-                                h->d_list, h->d_count, 0, 0.0, 0, R, nullptr, h->st);
+            e = sx::launch_weno(h->kg, h->kgas, h->ks, term_mask, W, h->wb, 0, 0.0, 0, R, nullptr, h->st);
     }
     if (e != hipSuccess) return sx_hip_fail(h, e, "sx_rhs");
     for (int b = 0; b < 2; ++b)
@@ -355,12 +360,10 @@ int sx_rk3_step(sx_handle* h, double dt)
             e = sx::launch_rhs(h->kg, h->kgas, h->ks, src, dst, h->Rprev, &sc, SX_ALL, h->pimg, h->st);
         if (e == hipSuccess && h->timing) e = sx_timed_end(h, ev);
         if (e == hipSuccess && h->ks.sensor) {
-            e = sx::launch_sensor_flags(h->kg, h->ks, src, h->d_theta, h->d_fx, h->d_fy, h->d_fz,
-                                        h->flag_override, h->d_list, h->d_count, h->st);
+            e = sx::launch_sensor_flags(h->kg, h->ks, src, h->wb, h->flag_override, h->st);
             if (e == hipSuccess)
-                e = sx::launch_weno(h->kg, h->kgas, h->ks, SX_ALL, src, h->d_fx, h->d_fy, h->d_fz,
-                                    h->d_list, h->d_count, 1, sc.cg, sc.write_prev, dst, h->Rprev,
-                                    h->st);
+                e = sx::launch_weno(h->kg, h->kgas, h->ks, SX_ALL, src, h->wb, 1, sc.cg, sc.write_prev,
+                                    dst, h->Rprev, h->st);
         }
         if (e != hipSuccess) return sx_hip_fail(h, e, "sx_rk3_step");
         h->ghosts_valid[h->cur] = true;
@@ -407,9 +410,9 @@ int sx_diagnostics(sx_handle* h, const double* R, sx_diag* out)
             double* Wc = h->W[h->cur];
             e = sx::launch_ghost_fill(h->kg, h->kgas, Wc, h->st);
             if (e == hipSuccess)
-                e = sx::launch_sensor_flags(h->kg, h->ks, Wc, h->d_theta, h->d_fx, h->d_fy, h->d_fz,
-                                            h->flag_override, h->d_list, h->d_count, h->st);
-            if (e == hipSuccess) e = sx::launch_count_flags(h->kg, h->d_fx, h->d_fy, h->d_fz, h->d_fcount, h->st);
+                e = sx::launch_sensor_flags(h->kg, h->ks, Wc, h->wb, h->flag_override, h->st);
+            if (e == hipSuccess)
+                e = sx::launch_count_flags(h->kg, h->wb.f[0], h->wb.f[1], h->wb.f[2], h->d_fcount, h->st);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(fc, h->d_fcount, sizeof fc, hipMemcpyDeviceToHost, h->st);
         }
@@ -454,11 +457,11 @@ int sx_set_flag_override(sx_handle* h, const unsigned char* fx, const unsigned c
     }
     if (!fx || !fy || !fz) return sx_fail(h, SX_EINVAL, "sx_set_flag_override: need all three arrays");
     const sx_grid& g = h->grid;
-    hipError_t e = hipMemcpyAsync(h->d_fx, fx, (size_t)g.nz * g.ny * (g.nx + 1), hipMemcpyDefault, h->st);
+    hipError_t e = hipMemcpyAsync(h->wb.f[0], fx, (size_t)g.nz * g.ny * (g.nx + 1), hipMemcpyDefault, h->st);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(h->d_fy, fy, (size_t)g.nz * (g.ny + 1) * g.nx, hipMemcpyDefault, h->st);
+        e = hipMemcpyAsync(h->wb.f[1], fy, (size_t)g.nz * (g.ny + 1) * g.nx, hipMemcpyDefault, h->st);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(h->d_fz, fz, (size_t)(g.nz + 1) * g.ny * g.nx, hipMemcpyDefault, h->st);
+        e = hipMemcpyAsync(h->wb.f[2], fz, (size_t)(g.nz + 1) * g.ny * g.nx, hipMemcpyDefault, h->st);
     if (e == hipSuccess) e = hipStreamSynchronize(h->st);
     if (e != hipSuccess) return sx_hip_fail(h, e, "sx_set_flag_override");
     h->flag_override = 1;

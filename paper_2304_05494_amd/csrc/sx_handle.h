@@ -29,13 +29,8 @@ struct sx_handle {
     sx::KScheme ks;
     double* d_metrics = nullptr;  // eta_y, eta_yy, y_eta  (3*ny)
     double* d_scratch = nullptr;  // reduction partials + results
-    // hybrid scheme (sensor on): theta, face flags, list of corrected nodes
-    double* d_theta = nullptr;
-    unsigned char* d_fx = nullptr;
-    unsigned char* d_fy = nullptr;
-    unsigned char* d_fz = nullptr;
-    int* d_list = nullptr;
-    int* d_count = nullptr;
+    // hybrid scheme (sensor on): theta, face flags, face and node lists, dF
+    sx::WenoBufs wb = {};
     unsigned long long* d_fcount = nullptr;
     int flag_override = 0;
     double* W[2] = {nullptr, nullptr};

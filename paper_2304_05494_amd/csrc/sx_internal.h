@@ -117,13 +117,20 @@ hipError_t launch_diagnostics(const KGrid& g, const KGas& gas, const KScheme& sc
                               int nscratch_blocks, hipStream_t st);
 hipError_t launch_max_rate(const KGrid& g, const KGas& gas, const double* W, double* scratch,
                            int nscratch_blocks, hipStream_t st);
-hipError_t launch_sensor_flags(const KGrid& g, const KScheme& sc, const double* W, double* theta,
-                               unsigned char* fx, unsigned char* fy, unsigned char* fz,
-                               int use_override, int* list, int* count, hipStream_t st);
+// Buffers of the hybrid (sensor + WENO) path.
+struct WenoBufs {
+    double* theta;              // sensor at interior nodes [nz][ny][nx]
+    unsigned char* f[3];        // face flags per direction (n_d + 1 faces per line)
+    int* flist[3];              // flagged faces per direction (face indices)
+    int* nlist;                 // nodes with a flagged face (interior indices)
+    int* counts;                // list lengths: faces x, y, z, nodes
+    double* dF[3];              // WENO minus central flux per face, [5][faces_d]
+};
+hipError_t launch_sensor_flags(const KGrid& g, const KScheme& sc, const double* W,
+                               const WenoBufs& b, int use_override, hipStream_t st);
 hipError_t launch_weno(const KGrid& g, const KGas& gas, const KScheme& sc, unsigned mask,
-                       const double* W, const unsigned char* fx, const unsigned char* fy,
-                       const unsigned char* fz, const int* list, const int* count, int mode,
-                       double cg, int write_prev, double* out, double* Rp, hipStream_t st);
+                       const double* W, const WenoBufs& b, int mode, double cg, int write_prev,
+                       double* out, double* Rp, hipStream_t st);
 hipError_t launch_count_flags(const KGrid& g, const unsigned char* fx, const unsigned char* fy,
                               const unsigned char* fz, unsigned long long* counts, hipStream_t st);
 

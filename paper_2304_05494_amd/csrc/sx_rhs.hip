@@ -297,13 +297,8 @@ __device__ __forceinline__ void march(Smem<S, TX, TY, R>& sm, const double* __re
     const R dxi = R(g.dxi), dzi = R(g.dzi);
     const R igM2 = R(gas.igM2);
     const long long col = g.base + (long long)j * g.sy + i;   // this column at k = 0
-    constexpr int NGY = (TY * HX + NT - 1) / NT;
-    R egy[NGY];                                               // eta_y of the D_y rows
-#pragma unroll
-    for (int a = 0; a < NGY; ++a) {
-        const int rr = (tid + a * NT) / HX;
-        egy[a] = (tid + a * NT < TY * HX && j0 + rr < g.ny) ? R(g.eta_y[j0 + rr]) : R(0);
-    }
+    static_assert(64 % TX == 0, "every row of the tile lies in one wave");
+    const R eyr = j < g.ny ? R(g.eta_y[j]) : R(0);            // eta_y of this row
 
     R m0[Q], m1[Q], m2[Q];   // D_x w, D_y w, D_x u + D_y v of this column
 #pragma unroll
@@ -493,24 +488,28 @@ __device__ __forceinline__ void march(Smem<S, TX, TY, R>& sm, const double* __re
             fetch_centre(k + 1);
         }
         sched_fence();
-        // y-derivatives of u, v at plane k over the x-extended columns
+        // y-derivatives of u, v at plane k over the x-extended columns of
+        // this thread's row. Only threads of the same row read them and a row
+        // lies in one wave, whose LDS accesses execute in order, so a
+        // wavefront-scope fence stands in for a workgroup barrier.
+        auto gy_at = [&](int hx) {
+            R su = 0, sv = 0;
 #pragma unroll
-        for (int a = 0; a < NGY; ++a) {
-            const int q = tid + a * NT;
-            const int hx = q % HX, rr = q / HX;
-            if (q < TY * HX && j0 + rr < g.ny) {
-                R su = 0, sv = 0;
-#pragma unroll
-                for (int l = 1; l <= S; ++l) {
-                    const int up = L::PREC * ((rr + S + l) * HX + hx), dn = L::PREC * ((rr + S - l) * HX + hx);
-                    su += R(Coef<S>::a[l]) * (so[up + 1] - so[dn + 1]);
-                    sv += R(Coef<S>::a[l]) * (so[up + 2] - so[dn + 2]);
-                }
-                gyl[0][rr][hx] = egy[a] * su;
-                gyl[1][rr][hx] = egy[a] * sv;
+            for (int l = 1; l <= S; ++l) {
+                const int up = L::PREC * ((ty + S + l) * HX + hx), dn = L::PREC * ((ty + S - l) * HX + hx);
+                su += R(Coef<S>::a[l]) * (so[up + 1] - so[dn + 1]);
+                sv += R(Coef<S>::a[l]) * (so[up + 2] - so[dn + 2]);
             }
+            gyl[0][ty][hx] = eyr * su;
+            gyl[1][ty][hx] = eyr * sv;
+        };
+        if (j < g.ny) {
+            gy_at(tx + S);
+            if (tx < 2 * S) gy_at(tx < S ? tx : TX + tx);
         }
-        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
         if (active) {
             R acc[NV] = {0, 0, 0, 0, 0};
@@ -661,13 +660,16 @@ __global__ void k_set_value(double* p, double v)
     if (threadIdx.x == 0) p[0] = v;
 }
 
-// Tile shapes: FP64 keeps one wave per SIMD (registers), so a 64x4 tile
-// (64x2 for the eighth-order stencil, LDS); FP32 halves registers and LDS,
-// so 64x8 tiles with two waves per SIMD.
+// Tile shapes: FP64 keeps one wave per SIMD (registers), so 256 threads per
+// workgroup: 32x8 up to sixth order (the smaller halo ratio, 38x14 staged
+// nodes per 256 outputs instead of 70x10, outweighs the shorter rows),
+// 64x2 for the eighth-order stencil (LDS); FP32 halves registers and LDS,
+// so 512-thread 64x8 tiles with two waves per SIMD (64x4 at eighth order).
 template <typename R, int S>
 struct Tile {
     static constexpr bool F32 = std::is_same<R, float>::value;
-    static constexpr int TX = 64, TY = F32 ? (S <= 3 ? 8 : 4) : (S <= 3 ? 4 : 2);
+    static constexpr int TX = (!F32 && S <= 3) ? 32 : 64;
+    static constexpr int TY = F32 ? (S <= 3 ? 8 : 4) : (S <= 3 ? 8 : 2);
     static constexpr int WPE = F32 ? 2 : 1;
 };
 
@@ -716,13 +718,14 @@ hipError_t launch_rhs(const KGrid& g, const KGas& gas, const KScheme& sc, const 
     return launch_rhs_R<double>(g, gas, sc, W, out, Rprev, step, mask, pimg, st);
 }
 
-// Batched tile shapes: variant 0 is the single-block tile; variant 1 halves
-// the x width and doubles the y height (same thread count), which keeps
-// every lane busy on blocks whose x extent is 32 or 96.
+// Batched tile shapes, at the single-block kernel's thread count: variant 0
+// is 64 wide, variant 1 is 32 wide (every lane busy on blocks whose x
+// extent is 32 or 96).
 template <typename R, int S, int V>
 struct BTile {
-    static constexpr int TX = V == 0 ? Tile<R, S>::TX : Tile<R, S>::TX / 2;
-    static constexpr int TY = V == 0 ? Tile<R, S>::TY : Tile<R, S>::TY * 2;
+    static constexpr int NT = Tile<R, S>::TX * Tile<R, S>::TY;
+    static constexpr int TX = V == 0 ? 64 : 32;
+    static constexpr int TY = NT / TX;
     static constexpr int WPE = Tile<R, S>::WPE;
 };
 

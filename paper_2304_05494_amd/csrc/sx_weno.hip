@@ -3,15 +3,21 @@
 // flux on flagged faces.
 //
 // The fused kernel (sx_rhs.hip) applies the central split-form flux on every
-// face. This pass then visits only nodes next to a flagged face and adds,
-// for each flagged face, the difference between the WENO characteristic
-// flux and the central flux of that face:
-//   dR_i = -scale (dF_{i+1/2} - dF_{i-1/2}),  dF = F_weno - F_central,
-// to the RHS (rhs mode) or, after the fused RK update, to the new state
-// (W' += dt gamma_k dR) and to the RK register (Rprev += dR). Each node
-// gathers its own faces (a face shared by two listed nodes is evaluated by
-// both), so results do not depend on list order and need no atomics on the
-// state.
+// face. This pass then corrects the flagged faces only, in three steps:
+//   1. k_flags: every node decides the flags of the faces it owns (the face
+//      after it along each direction, plus the first face of each line) and
+//      appends flagged faces to one list per direction and itself to a node
+//      list when any of its six faces is flagged (one atomic per wave);
+//   2. k_weno_face: one thread per flagged face evaluates
+//      dF = F_weno - F_central once and stores it by face index, so the
+//      wave's lanes all run the same characteristic-flux code (no per-node
+//      branching over faces and directions);
+//   3. k_weno_node: one thread per listed node gathers the dF of its flagged
+//      faces in a fixed order, dR = -scale (dF_{i+1/2} - dF_{i-1/2}) per
+//      direction, and adds dR to the RHS (rhs mode) or, after the fused RK
+//      update, to the new state (W' += dt gamma_k dR) and to the RK register
+//      (Rprev += dR).
+// The order of the lists does not change any result.
 //
 // Sensor: theta = max(0, -div u / sqrt(div u^2 + |curl u|^2 + eps^2)) with
 // second-order central differences at interior nodes; a face i+1/2 uses WENO
@@ -75,16 +81,10 @@ __global__ void __launch_bounds__(WB) k_theta(KGrid g, double eps, const double*
 }
 
 // Face flags: f[d] holds n_d + 1 faces per line (entry f is the face
-// between nodes f-1 and f). One thread per interior node writes its "+"
-// faces, node 0 of a line also its "-" face; it appends itself to the list
-// when any of its six faces is flagged. A flags override (three arrays
-// uploaded by the caller) replaces the sensor.
+// between nodes f-1 and f). Node (i, j, k) decides the face after it along
+// each direction and, for i = 0 (j = 0, k = 0), the first face of its line.
 __global__ void __launch_bounds__(WB) k_flags(KGrid g, int r, double thr,
-                                              const double* __restrict__ theta,
-                                              unsigned char* __restrict__ fx,
-                                              unsigned char* __restrict__ fy,
-                                              unsigned char* __restrict__ fz, int use_override,
-                                              int* __restrict__ list, int* __restrict__ count)
+                                              const double* __restrict__ theta, WenoBufs b)
 {
     const long long m = (long long)blockIdx.x * WB + threadIdx.x;
     if (m >= g.nint) return;
@@ -92,17 +92,17 @@ __global__ void __launch_bounds__(WB) k_flags(KGrid g, int r, double thr,
     const long long jk = m / g.nx;
     const int j = (int)(jk % g.ny);
     const int k = (int)(jk / g.ny);
-    auto th = [&](int a, int b, int c) -> double {
+    auto th = [&](int a, int bb, int c) -> double {
         const int ia = map_ghost(a, g.nx, g.bc[0], g.bc[1]);
-        const int jb = map_ghost(b, g.ny, g.bc[2], g.bc[3]);
+        const int jb = map_ghost(bb, g.ny, g.bc[2], g.bc[3]);
         const int kc = map_ghost(c, g.nz, g.bc[4], g.bc[5]);
         return theta[((long long)kc * g.ny + jb) * g.nx + ia];
     };
-    // flag of the face after node (a,b,c) along d
-    auto face = [&](int d, int a, int b, int c) -> unsigned char {
+    // flag of the face after node (a,bb,c) along d
+    auto face = [&](int d, int a, int bb, int c) -> unsigned char {
         double mx = 0.0;
         for (int t = -r + 1; t <= r; ++t) {
-            const double v = d == 0 ? th(a + t, b, c) : (d == 1 ? th(a, b + t, c) : th(a, b, c + t));
+            const double v = d == 0 ? th(a + t, bb, c) : (d == 1 ? th(a, bb + t, c) : th(a, bb, c + t));
             mx = v > mx ? v : mx;
         }
         return mx > thr ? 1 : 0;
@@ -110,266 +110,375 @@ __global__ void __launch_bounds__(WB) k_flags(KGrid g, int r, double thr,
     const long long ix = ((long long)k * g.ny + j) * (g.nx + 1) + i;       // face i-1/2 in fx
     const long long iy = ((long long)k * (g.ny + 1) + j) * g.nx + i;       // face j-1/2 in fy
     const long long iz = ((long long)k * g.ny + j) * g.nx + i;             // face k-1/2 in fz
-    const long long sfy = g.nx, sfz = (long long)g.ny * g.nx;
-    unsigned char any = 0;
-    if (use_override) {
-        any = fx[ix] | fx[ix + 1] | fy[iy] | fy[iy + sfy] | fz[iz] | fz[iz + sfz];
-    } else {
-        const unsigned char xp = face(0, i, j, k), yp = face(1, i, j, k), zp = face(2, i, j, k);
-        const unsigned char xm = face(0, i - 1, j, k), ym = face(1, i, j - 1, k), zm = face(2, i, j, k - 1);
-        fx[ix + 1] = xp;
-        fy[iy + sfy] = yp;
-        fz[iz + sfz] = zp;
-        if (i == 0) fx[ix] = xm;
-        if (j == 0) fy[iy] = ym;
-        if (k == 0) fz[iz] = zm;
-        any = xp | yp | zp | xm | ym | zm;
-    }
-    if (any) {
-        const int slot = atomicAdd(count, 1);
-        list[slot] = (int)m;
-    }
+    b.f[0][ix + 1] = face(0, i, j, k);
+    b.f[1][iy + g.nx] = face(1, i, j, k);
+    b.f[2][iz + (long long)g.ny * g.nx] = face(2, i, j, k);
+    if (i == 0) b.f[0][ix] = face(0, i - 1, j, k);
+    if (j == 0) b.f[1][iy] = face(1, i, j - 1, k);
+    if (k == 0) b.f[2][iz] = face(2, i, j, k - 1);
 }
 
-__global__ void k_zero_int(int* p) { *p = 0; }
+// Wave-aggregated append into a workgroup's LDS cursor: returns this lane's
+// slot (relative to the workgroup's block of the list) or -1.
+__device__ __forceinline__ int wave_slot(bool pred, int* cursor)
+{
+    const unsigned long long mask = __ballot(pred);
+    if (!mask) return -1;
+    const int lane = __lane_id();
+    const int leader = __ffsll((long long)mask) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(cursor, __popcll(mask));
+    base = __shfl(base, leader);
+    return pred ? base + __popcll(mask & ((1ull << lane) - 1ull)) : -1;
+}
 
-struct Prim {
-    double r, u, v, w, p, H, W[5];
-};
+// Lists from the face flags. Workgroup w owns nodes [w*WB*LPT, (w+1)*WB*LPT):
+// a counting pass sizes its share of each list (flagged faces it owns per
+// direction, and its nodes with any flagged face), one global atomic per
+// list reserves the space, a second pass writes the entries.
+constexpr int LPT = 16;   // nodes per thread
+__global__ void __launch_bounds__(WB) k_lists(KGrid g, WenoBufs b)
+{
+    __shared__ int cur[4], base[4];
+    if (threadIdx.x < 4) cur[threadIdx.x] = 0;
+    __syncthreads();
+    const long long m0 = (long long)blockIdx.x * WB * LPT;
+    const long long sfy = g.nx, sfz = (long long)g.ny * g.nx;
+    auto visit = [&](bool write) {
+        for (int it = 0; it < LPT; ++it) {
+            const long long m = m0 + (long long)it * WB + threadIdx.x;
+            const bool in = m < g.nint;
+            bool own[6] = {false, false, false, false, false, false}, node = false;
+            long long e[6] = {0, 0, 0, 0, 0, 0};
+            if (in) {
+                const int i = (int)(m % g.nx);
+                const long long jk = m / g.nx;
+                const int j = (int)(jk % g.ny);
+                const int k = (int)(jk / g.ny);
+                const long long ix = ((long long)k * g.ny + j) * (g.nx + 1) + i;
+                const long long iy = ((long long)k * (g.ny + 1) + j) * g.nx + i;
+                const long long iz = ((long long)k * g.ny + j) * g.nx + i;
+                const bool xm = b.f[0][ix], xp = b.f[0][ix + 1];
+                const bool ym = b.f[1][iy], yp = b.f[1][iy + sfy];
+                const bool zm = b.f[2][iz], zp = b.f[2][iz + sfz];
+                own[0] = xp; e[0] = ix + 1;
+                own[1] = i == 0 && xm; e[1] = ix;
+                own[2] = yp; e[2] = iy + sfy;
+                own[3] = j == 0 && ym; e[3] = iy;
+                own[4] = zp; e[4] = iz + sfz;
+                own[5] = k == 0 && zm; e[5] = iz;
+                node = xm || xp || ym || yp || zm || zp;
+            }
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                const int slot = wave_slot(own[q], &cur[q / 2]);
+                if (write && slot >= 0) b.flist[q / 2][base[q / 2] + slot] = (int)e[q];
+            }
+            const int slot = wave_slot(node, &cur[3]);
+            if (write && slot >= 0) b.nlist[base[3] + slot] = (int)m;
+        }
+    };
+    visit(false);
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        base[threadIdx.x] = cur[threadIdx.x] ? atomicAdd(&b.counts[threadIdx.x], cur[threadIdx.x]) : 0;
+        cur[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    visit(true);
+}
+
+__global__ void k_zero_counts(int* p)
+{
+    if (threadIdx.x < 4) p[threadIdx.x] = 0;
+}
 
 // Jiang-Shu WENO reconstruction at i+1/2 from v[0 .. 2r-2] = v_{i-r+1 .. i+r-1}
-template <int RW>
-__device__ __forceinline__ double weno_left(const double* v, double eps)
+template <int RW, typename R>
+__device__ __forceinline__ R weno_left(const R* v, R eps)
 {
     if (RW == 1) return v[0];
     if (RW == 2) {
-        const double vm = v[0], v0 = v[1], vp = v[2];
-        const double q0 = 0.5 * (-vm + 3.0 * v0), q1 = 0.5 * (v0 + vp);
-        const double b0 = (v0 - vm) * (v0 - vm), b1 = (vp - v0) * (vp - v0);
-        const double a0 = (1.0 / 3.0) / ((eps + b0) * (eps + b0));
-        const double a1 = (2.0 / 3.0) / ((eps + b1) * (eps + b1));
+        const R vm = v[0], v0 = v[1], vp = v[2];
+        const R q0 = R(0.5) * (-vm + R(3) * v0), q1 = R(0.5) * (v0 + vp);
+        const R b0 = (v0 - vm) * (v0 - vm), b1 = (vp - v0) * (vp - v0);
+        const R a0 = R(1.0 / 3.0) / ((eps + b0) * (eps + b0));
+        const R a1 = R(2.0 / 3.0) / ((eps + b1) * (eps + b1));
         return (a0 * q0 + a1 * q1) / (a0 + a1);
     }
-    const double vmm = v[0], vm = v[1], v0 = v[2], vp = v[3], vpp = v[4];
-    const double q0 = (2.0 * vmm - 7.0 * vm + 11.0 * v0) * (1.0 / 6.0);
-    const double q1 = (-vm + 5.0 * v0 + 2.0 * vp) * (1.0 / 6.0);
-    const double q2 = (2.0 * v0 + 5.0 * vp - vpp) * (1.0 / 6.0);
-    double t, b0, b1, b2;
-    t = vmm - 2.0 * vm + v0; b0 = (13.0 / 12.0) * t * t;
-    t = vmm - 4.0 * vm + 3.0 * v0; b0 += 0.25 * t * t;
-    t = vm - 2.0 * v0 + vp; b1 = (13.0 / 12.0) * t * t;
-    t = vm - vp; b1 += 0.25 * t * t;
-    t = v0 - 2.0 * vp + vpp; b2 = (13.0 / 12.0) * t * t;
-    t = 3.0 * v0 - 4.0 * vp + vpp; b2 += 0.25 * t * t;
-    const double a0 = 0.1 / ((eps + b0) * (eps + b0));
-    const double a1 = 0.6 / ((eps + b1) * (eps + b1));
-    const double a2 = 0.3 / ((eps + b2) * (eps + b2));
+    const R vmm = v[0], vm = v[1], v0 = v[2], vp = v[3], vpp = v[4];
+    const R q0 = (R(2) * vmm - R(7) * vm + R(11) * v0) * R(1.0 / 6.0);
+    const R q1 = (-vm + R(5) * v0 + R(2) * vp) * R(1.0 / 6.0);
+    const R q2 = (R(2) * v0 + R(5) * vp - vpp) * R(1.0 / 6.0);
+    R t, b0, b1, b2;
+    t = vmm - R(2) * vm + v0; b0 = R(13.0 / 12.0) * t * t;
+    t = vmm - R(4) * vm + R(3) * v0; b0 += R(0.25) * t * t;
+    t = vm - R(2) * v0 + vp; b1 = R(13.0 / 12.0) * t * t;
+    t = vm - vp; b1 += R(0.25) * t * t;
+    t = v0 - R(2) * vp + vpp; b2 = R(13.0 / 12.0) * t * t;
+    t = R(3) * v0 - R(4) * vp + vpp; b2 += R(0.25) * t * t;
+    const R a0 = R(0.1) / ((eps + b0) * (eps + b0));
+    const R a1 = R(0.6) / ((eps + b1) * (eps + b1));
+    const R a2 = R(0.3) / ((eps + b2) * (eps + b2));
     return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
 }
 
-// WENO minus central flux of the face between stencil positions HALF-1 and
-// HALF (nodes nd[0 .. 2*HALF-1], face in the middle) along direction d.
-template <int L, int RW, int HALF>
-__device__ void face_delta(const Prim (&nd)[2 * HALF], int d, const KGas& gas, double eps,
-                           double (&dF)[NV])
+// Values of one stencil node, in the face's frame: x[0..4] = (rho,
+// rho u_n, rho u_t1, rho u_t2, rho E), primitive u, v, w, H, p.
+template <typename R>
+struct FNode {
+    R x[NV];
+    R r, u, v, w, H, p;
+};
+
+// WENO minus central flux of the face between stencil nodes HALF-1 and HALF
+// (node q at W + n0 + q s) along direction d; FP64 primitives, arithmetic in R.
+template <int L, int RW, int HALF, int d, typename R>
+__device__ __forceinline__ void face_delta(const double* __restrict__ W, long long n0, long long s,
+                                           long long sv, const KGas& gas, R eps, double (&dF)[NV])
 {
+    constexpr int perm[NV] = {0, 1 + d, 1 + (d + 1) % 3, 1 + (d + 2) % 3, 4};
+    FNode<R> nd[2 * HALF];
+#pragma unroll
+    for (int q = 0; q < 2 * HALF; ++q) {
+        double w5[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) w5[v] = W[n0 + q * s + v * sv];
+        const double ri = 1.0 / w5[0];
+        const double u = w5[1] * ri, v = w5[2] * ri, w = w5[3] * ri;
+        const double p = gas.gm1 * (w5[4] - 0.5 * w5[0] * (u * u + v * v + w * w));
+        FNode<R>& f = nd[q];
+#pragma unroll
+        for (int c = 0; c < NV; ++c) f.x[c] = R(w5[perm[c]]);
+        f.r = R(w5[0]);
+        f.u = R(u);
+        f.v = R(v);
+        f.w = R(w);
+        f.p = R(p);
+        f.H = R((w5[4] + p) * ri);
+    }
+    auto vel = [&](const FNode<R>& q, int c) { return c == 0 ? q.u : (c == 1 ? q.v : q.w); };
+
     // central split-form face flux, pairs (A, B) = (c-m, c-m+l), c = HALF-1
-    double Fc[NV] = {0, 0, 0, 0, 0}, P = 0.0;
+    R Fc[NV] = {0, 0, 0, 0, 0}, P = R(0);
 #pragma unroll
     for (int l = 1; l <= L; ++l) {
-        const double cl = 2.0 * Coef<L>::a[l];
+        const R cl = R(2.0 * Coef<L>::a[l]);
 #pragma unroll
         for (int mm = 0; mm < l; ++mm) {
-            const Prim& A = nd[HALF - 1 - mm];
-            const Prim& B = nd[HALF - 1 - mm + l];
-            const double udA = d == 0 ? A.u : (d == 1 ? A.v : A.w);
-            const double udB = d == 0 ? B.u : (d == 1 ? B.v : B.w);
-            const double mf = 0.125 * (A.r + B.r) * (udA + udB);
-            Fc[0] += cl * (mf * 2.0);
+            const FNode<R>& A = nd[HALF - 1 - mm];
+            const FNode<R>& B = nd[HALF - 1 - mm + l];
+            const R mf = R(0.125) * (A.r + B.r) * (vel(A, d) + vel(B, d));
+            Fc[0] += cl * (mf * R(2));
             Fc[1] += cl * (mf * (A.u + B.u));
             Fc[2] += cl * (mf * (A.v + B.v));
             Fc[3] += cl * (mf * (A.w + B.w));
             Fc[4] += cl * (mf * (A.H + B.H));
-            P += cl * (0.5 * (A.p + B.p));
+            P += cl * (R(0.5) * (A.p + B.p));
         }
     }
     Fc[1 + d] += P;
 
     // characteristic basis at the Roe average of the two face nodes
-    const int perm[NV] = {0, 1 + d, 1 + (d + 1) % 3, 1 + (d + 2) % 3, 4};
-    const Prim& a = nd[HALF - 1];
-    const Prim& b = nd[HALF];
-    const double sa = sqrt(a.r), sb = sqrt(b.r), si = 1.0 / (sa + sb);
-    auto vel = [&](const Prim& q, int c) { return c == 0 ? q.u : (c == 1 ? q.v : q.w); };
-    const double un = (sa * vel(a, d) + sb * vel(b, d)) * si;
-    const double ut1 = (sa * vel(a, (d + 1) % 3) + sb * vel(b, (d + 1) % 3)) * si;
-    const double ut2 = (sa * vel(a, (d + 2) % 3) + sb * vel(b, (d + 2) % 3)) * si;
-    const double Hb = (sa * a.H + sb * b.H) * si;
-    const double q2 = un * un + ut1 * ut1 + ut2 * ut2;
-    const double cb = sqrt(gas.gm1 * (Hb - 0.5 * q2));
-    const double b1 = gas.gm1 / (cb * cb);
-    const double b2 = 0.5 * q2 * b1;
-    const double ic = 1.0 / cb;
-    const double Lm[5][5] = {
-        {0.5 * (b2 + un * ic), 0.5 * (-b1 * un - ic), -0.5 * b1 * ut1, -0.5 * b1 * ut2, 0.5 * b1},
-        {-ut1, 0.0, 1.0, 0.0, 0.0},
-        {-ut2, 0.0, 0.0, 1.0, 0.0},
-        {1.0 - b2, b1 * un, b1 * ut1, b1 * ut2, -b1},
-        {0.5 * (b2 - un * ic), 0.5 * (-b1 * un + ic), -0.5 * b1 * ut1, -0.5 * b1 * ut2, 0.5 * b1}};
+    const FNode<R>& a = nd[HALF - 1];
+    const FNode<R>& bn = nd[HALF];
+    const R sa = sqrt(a.r), sb = sqrt(bn.r), si = R(1) / (sa + sb);
+    const R un = (sa * vel(a, d) + sb * vel(bn, d)) * si;
+    const R ut1 = (sa * vel(a, (d + 1) % 3) + sb * vel(bn, (d + 1) % 3)) * si;
+    const R ut2 = (sa * vel(a, (d + 2) % 3) + sb * vel(bn, (d + 2) % 3)) * si;
+    const R Hb = (sa * a.H + sb * bn.H) * si;
+    const R q2 = un * un + ut1 * ut1 + ut2 * ut2;
+    const R cb = sqrt(R(gas.gm1) * (Hb - R(0.5) * q2));
+    const R b1 = R(gas.gm1) / (cb * cb);
+    const R b2 = R(0.5) * q2 * b1;
+    const R ic = R(1) / cb;
+    // rows of the left eigenvector matrix applied to a vector x
+    auto lrow = [&](int kk, const R (&x)[NV]) -> R {
+        const R tang = -R(0.5) * b1 * (ut1 * x[2] + ut2 * x[3]);
+        switch (kk) {
+        case 0: return R(0.5) * (b2 + un * ic) * x[0] + R(0.5) * (-b1 * un - ic) * x[1] + tang + R(0.5) * b1 * x[4];
+        case 1: return -ut1 * x[0] + x[2];
+        case 2: return -ut2 * x[0] + x[3];
+        case 3: return (R(1) - b2) * x[0] + b1 * (un * x[1] + ut1 * x[2] + ut2 * x[3]) - b1 * x[4];
+        default: return R(0.5) * (b2 - un * ic) * x[0] + R(0.5) * (-b1 * un + ic) * x[1] + tang + R(0.5) * b1 * x[4];
+        }
+    };
 
     constexpr int NS = 2 * RW;          // WENO stencil nodes
     constexpr int OFF = HALF - RW;      // first WENO node in nd[]
-    double g[NS][NV], qc[NS][NV], lam[NV] = {0, 0, 0, 0, 0};
+    // local Lax-Friedrichs speeds: largest |u_n - c|, |u_n|, |u_n + c| over the stencil
+    R lm = R(0), l0 = R(0), lp = R(0);
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
-        const Prim& n = nd[OFF + t];
-        const double unt = vel(n, d);
-        const double ct = sqrt(gas.gamma * n.p / n.r);
-        const double ev[NV] = {fabs(unt - ct), fabs(unt), fabs(unt), fabs(unt), fabs(unt + ct)};
-        double wp[NV], fp[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) wp[v] = n.W[perm[v]];
-        fp[0] = wp[0] * unt;
-        fp[1] = wp[1] * unt + n.p;
-        fp[2] = wp[2] * unt;
-        fp[3] = wp[3] * unt;
-        fp[4] = (wp[4] + n.p) * unt;
-#pragma unroll
-        for (int kk = 0; kk < NV; ++kk) {
-            double sg = 0.0, sq = 0.0;
-#pragma unroll
-            for (int mm = 0; mm < NV; ++mm) {
-                sg += Lm[kk][mm] * fp[mm];
-                sq += Lm[kk][mm] * wp[mm];
-            }
-            g[t][kk] = sg;
-            qc[t][kk] = sq;
-            lam[kk] = ev[kk] > lam[kk] ? ev[kk] : lam[kk];
-        }
+        const FNode<R>& n = nd[OFF + t];
+        const R unt = vel(n, d);
+        const R ct = sqrt(R(gas.gamma) * n.p / n.r);
+        lm = fmax(lm, fabs(unt - ct));
+        l0 = fmax(l0, fabs(unt));
+        lp = fmax(lp, fabs(unt + ct));
     }
-    double Fh[NV];
+    R Fh[NV];
 #pragma unroll
     for (int kk = 0; kk < NV; ++kk) {
-        double vl[2 * RW - 1], vr[2 * RW - 1];
+        const R lam = kk == 0 ? lm : (kk == 4 ? lp : l0);
+        R gq[NS][2];
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+            const FNode<R>& n = nd[OFF + t];
+            const R unt = vel(n, d);
+            R fl[NV];
+            fl[0] = n.x[1];
+            fl[1] = n.x[1] * unt + n.p;
+            fl[2] = n.x[2] * unt;
+            fl[3] = n.x[3] * unt;
+            fl[4] = (n.x[4] + n.p) * unt;
+            gq[t][0] = lrow(kk, fl);
+            gq[t][1] = lrow(kk, n.x);
+        }
+        R vl[2 * RW - 1], vr[2 * RW - 1];
 #pragma unroll
         for (int t = 0; t < 2 * RW - 1; ++t) {
-            vl[t] = 0.5 * (g[t][kk] + lam[kk] * qc[t][kk]);
-            vr[t] = 0.5 * (g[NS - 1 - t][kk] - lam[kk] * qc[NS - 1 - t][kk]);
+            vl[t] = R(0.5) * (gq[t][0] + lam * gq[t][1]);
+            vr[t] = R(0.5) * (gq[NS - 1 - t][0] - lam * gq[NS - 1 - t][1]);
         }
-        Fh[kk] = weno_left<RW>(vl, eps) + weno_left<RW>(vr, eps);
+        Fh[kk] = weno_left<RW, R>(vl, eps) + weno_left<RW, R>(vr, eps);
     }
     // right eigenvectors applied to the reconstructed characteristic flux
-    const double Rm[5][5] = {
-        {1.0, 0.0, 0.0, 1.0, 1.0},
-        {un - cb, 0.0, 0.0, un, un + cb},
-        {ut1, 1.0, 0.0, ut1, ut1},
-        {ut2, 0.0, 1.0, ut2, ut2},
-        {Hb - un * cb, ut1, ut2, 0.5 * q2, Hb + un * cb}};
+    const R G[NV] = {Fh[0] + Fh[3] + Fh[4],
+                     (un - cb) * Fh[0] + un * Fh[3] + (un + cb) * Fh[4],
+                     ut1 * (Fh[0] + Fh[3] + Fh[4]) + Fh[1],
+                     ut2 * (Fh[0] + Fh[3] + Fh[4]) + Fh[2],
+                     (Hb - un * cb) * Fh[0] + ut1 * Fh[1] + ut2 * Fh[2] + R(0.5) * q2 * Fh[3] +
+                         (Hb + un * cb) * Fh[4]};
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        double s = 0.0;
-#pragma unroll
-        for (int kk = 0; kk < NV; ++kk) s += Rm[v][kk] * Fh[kk];
-        dF[perm[v]] = s - Fc[perm[v]];
-    }
+    for (int v = 0; v < NV; ++v) dF[perm[v]] = double(G[v]) - double(Fc[perm[v]]);
 }
 
-__device__ __forceinline__ Prim load_node(const double* __restrict__ W, long long q, long long sv,
-                                          const KGas& gas)
-{
-    Prim n;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) n.W[v] = W[q + v * sv];
-    n.r = n.W[0];
-    const double ri = 1.0 / n.r;
-    n.u = n.W[1] * ri;
-    n.v = n.W[2] * ri;
-    n.w = n.W[3] * ri;
-    n.p = gas.gm1 * (n.W[4] - 0.5 * n.r * (n.u * n.u + n.v * n.v + n.w * n.w));
-    n.H = (n.W[4] + n.p) * ri;
-    return n;
-}
-
-// Correction of one listed node: for each direction with a flagged face,
-// dR -= scale (dF_plus - dF_minus). mode 0: R += dR (rhs); mode 1: update
-// (out = W', cg = dt gamma_k; Rp += dR when write_prev).
-template <int L, int RW>
-__global__ void __launch_bounds__(WB) k_weno(KGrid g, KGas gas, double eps, unsigned mask,
-                                             const double* __restrict__ W,
-                                             const unsigned char* __restrict__ fx,
-                                             const unsigned char* __restrict__ fy,
-                                             const unsigned char* __restrict__ fz,
-                                             const int* __restrict__ list,
-                                             const int* __restrict__ count, int mode, double cg,
-                                             int write_prev, double* __restrict__ out,
-                                             double* __restrict__ Rp)
+// One thread per flagged face of direction d (grid-stride over the list):
+// dF of the face, stored at its face index.
+template <int L, int RW, int d, typename R>
+__global__ void __launch_bounds__(WB) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : 2)))
+k_weno_face(KGrid g, KGas gas, double eps,
+                                                  const double* __restrict__ W, WenoBufs b)
 {
     constexpr int HALF = L > RW ? L : RW;
-    const int t = blockIdx.x * WB + threadIdx.x;
-    if (t >= *count) return;
-    const long long m = list[t];
-    const int i = (int)(m % g.nx);
-    const long long jk = m / g.nx;
-    const int j = (int)(jk % g.ny);
-    const int k = (int)(jk / g.ny);
-    const long long n = g.base + (long long)k * g.sz + (long long)j * g.sy + i;
-    const long long ix = ((long long)k * g.ny + j) * (g.nx + 1) + i;
-    const long long iy = ((long long)k * (g.ny + 1) + j) * g.nx + i;
-    const long long iz = ((long long)k * g.ny + j) * g.nx + i;
-    const unsigned char fl[3][2] = {{fx[ix], fx[ix + 1]},
-                                    {fy[iy], fy[iy + g.nx]},
-                                    {fz[iz], fz[iz + (long long)g.ny * g.nx]}};
-    double dR[NV] = {0, 0, 0, 0, 0};
-    for (int d = 0; d < 3; ++d) {
-        if (!(mask & (1u << d))) continue;
-        if (!fl[d][0] && !fl[d][1]) continue;
-        const long long s = d == 0 ? 1 : (d == 1 ? g.sy : g.sz);
-        const double scale = d == 0 ? g.dxi : (d == 1 ? g.eta_y[j] : g.dzi);
-        // nodes i-HALF .. i+HALF: the two faces share 2*HALF-1 of them
-        Prim nd[2 * HALF + 1];
-#pragma unroll
-        for (int q = 0; q < 2 * HALF + 1; ++q) nd[q] = load_node(W, n + (q - HALF) * s, g.sv, gas);
-#pragma unroll
-        for (int side = 0; side < 2; ++side) {
-            if (!fl[d][side]) continue;
-            Prim sub[2 * HALF];
-#pragma unroll
-            for (int q = 0; q < 2 * HALF; ++q) sub[q] = nd[q + side];   // face i-1/2 (side 0) / i+1/2
-            double dF[NV];
-            face_delta<L, RW, HALF>(sub, d, gas, eps, dF);
-            const double sg = side == 1 ? -scale : scale;
-#pragma unroll
-            for (int v = 0; v < NV; ++v) dR[v] += sg * dF[v];
+    const int nf = b.counts[d];
+    const long long nface = d == 0 ? (long long)g.nz * g.ny * (g.nx + 1)
+                                   : (d == 1 ? (long long)g.nz * (g.ny + 1) * g.nx
+                                             : (long long)(g.nz + 1) * g.ny * g.nx);
+    const int* __restrict__ fl = b.flist[d];
+    double* __restrict__ out = b.dF[d];
+    const long long s = d == 0 ? 1 : (d == 1 ? g.sy : g.sz);
+    for (int t = blockIdx.x * WB + threadIdx.x; t < nf; t += gridDim.x * WB) {
+        const long long e = fl[t];
+        int i, j, k;   // the node after the face
+        if (d == 0) {
+            i = (int)(e % (g.nx + 1));
+            const long long jk = e / (g.nx + 1);
+            j = (int)(jk % g.ny);
+            k = (int)(jk / g.ny);
+        } else if (d == 1) {
+            i = (int)(e % g.nx);
+            const long long jk = e / g.nx;
+            j = (int)(jk % (g.ny + 1));
+            k = (int)(jk / (g.ny + 1));
+        } else {
+            i = (int)(e % g.nx);
+            const long long jk = e / g.nx;
+            j = (int)(jk % g.ny);
+            k = (int)(jk / g.ny);
         }
+        const long long n = g.base + (long long)k * g.sz + (long long)j * g.sy + i;
+        double dF[NV];
+        face_delta<L, RW, HALF, d, R>(W, n - HALF * s, s, g.sv, gas, R(eps), dF);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) out[v * nface + e] = dF[v];
     }
-    if (mode == 0) {
+}
+
+// One thread per listed node (grid-stride): dR from the dF of its flagged
+// faces, directions x, y, z and within each the "-" face then the "+" face.
+// mode 0: R += dR (rhs); mode 1: update (out = W', cg = dt gamma_k;
+// Rp += dR when write_prev).
+__global__ void __launch_bounds__(WB) k_weno_node(KGrid g, unsigned mask, WenoBufs b, int mode,
+                                                  double cg, int write_prev, double* __restrict__ out,
+                                                  double* __restrict__ Rp)
+{
+    const int nn = b.counts[3];
+    const long long nfx = (long long)g.nz * g.ny * (g.nx + 1);
+    const long long nfy = (long long)g.nz * (g.ny + 1) * g.nx;
+    const long long nfz = (long long)(g.nz + 1) * g.ny * g.nx;
+    for (int t = blockIdx.x * WB + threadIdx.x; t < nn; t += gridDim.x * WB) {
+        const long long m = b.nlist[t];
+        const int i = (int)(m % g.nx);
+        const long long jk = m / g.nx;
+        const int j = (int)(jk % g.ny);
+        const int k = (int)(jk / g.ny);
+        const long long fidx[3][2] = {{((long long)k * g.ny + j) * (g.nx + 1) + i, 0},
+                                      {((long long)k * (g.ny + 1) + j) * g.nx + i, 0},
+                                      {((long long)k * g.ny + j) * g.nx + i, 0}};
+        const long long step[3] = {1, g.nx, (long long)g.ny * g.nx};
+        const long long nface[3] = {nfx, nfy, nfz};
+        double dR[NV] = {0, 0, 0, 0, 0};
+        for (int d = 0; d < 3; ++d) {
+            if (!(mask & (1u << d))) continue;
+            const double scale = d == 0 ? g.dxi : (d == 1 ? g.eta_y[j] : g.dzi);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) out[v * g.nint + m] += dR[v];
-    } else {
+            for (int side = 0; side < 2; ++side) {
+                const long long e = fidx[d][0] + side * step[d];
+                if (!b.f[d][e]) continue;
+                const double sg = side == 1 ? -scale : scale;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            out[v * g.sv + n] = __builtin_fma(cg, dR[v], out[v * g.sv + n]);
-            if (write_prev) Rp[v * g.nint + m] += dR[v];
+                for (int v = 0; v < NV; ++v) dR[v] += sg * b.dF[d][v * nface[d] + e];
+            }
+        }
+        if (mode == 0) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) out[v * g.nint + m] += dR[v];
+        } else {
+            const long long n = g.base + (long long)k * g.sz + (long long)j * g.sy + i;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                out[v * g.sv + n] = __builtin_fma(cg, dR[v], out[v * g.sv + n]);
+                if (write_prev) Rp[v * g.nint + m] += dR[v];
+            }
         }
     }
 }
 
-template <int L>
-hipError_t launch_weno_L(int RW, const KGrid& g, const KGas& gas, double eps, unsigned mask,
-                         const double* W, const unsigned char* fx, const unsigned char* fy,
-                         const unsigned char* fz, const int* list, const int* count, int mode,
-                         double cg, int write_prev, double* out, double* Rp, hipStream_t st)
+int persistent_blocks()
 {
-    const dim3 grid((unsigned)((g.nint + WB - 1) / WB));
-    switch (RW) {
-    case 1: hipLaunchKernelGGL((k_weno<L, 1>), grid, dim3(WB), 0, st, g, gas, eps, mask, W, fx, fy, fz,
-                               list, count, mode, cg, write_prev, out, Rp); break;
-    case 2: hipLaunchKernelGGL((k_weno<L, 2>), grid, dim3(WB), 0, st, g, gas, eps, mask, W, fx, fy, fz,
-                               list, count, mode, cg, write_prev, out, Rp); break;
-    default: hipLaunchKernelGGL((k_weno<L, 3>), grid, dim3(WB), 0, st, g, gas, eps, mask, W, fx, fy,
-                                fz, list, count, mode, cg, write_prev, out, Rp); break;
+    static int nb = 0;
+    if (!nb) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 256;
+        nb = 8 * cus;
     }
+    return nb;
+}
+
+template <int L, int RW, typename R>
+hipError_t launch_faces(const KGrid& g, const KGas& gas, double eps, unsigned mask, const double* W,
+                        const WenoBufs& b, hipStream_t st)
+{
+    const dim3 grid(persistent_blocks());
+    if (mask & SX_CONV_X) hipLaunchKernelGGL((k_weno_face<L, RW, 0, R>), grid, dim3(WB), 0, st, g, gas, eps, W, b);
+    if (mask & SX_CONV_Y) hipLaunchKernelGGL((k_weno_face<L, RW, 1, R>), grid, dim3(WB), 0, st, g, gas, eps, W, b);
+    if (mask & SX_CONV_Z) hipLaunchKernelGGL((k_weno_face<L, RW, 2, R>), grid, dim3(WB), 0, st, g, gas, eps, W, b);
     return hipGetLastError();
+}
+
+template <int L, typename R>
+hipError_t launch_faces_L(int RW, const KGrid& g, const KGas& gas, double eps, unsigned mask,
+                          const double* W, const WenoBufs& b, hipStream_t st)
+{
+    switch (RW) {
+    case 1: return launch_faces<L, 1, R>(g, gas, eps, mask, W, b, st);
+    case 2: return launch_faces<L, 2, R>(g, gas, eps, mask, W, b, st);
+    default: return launch_faces<L, 3, R>(g, gas, eps, mask, W, b, st);
+    }
 }
 
 // Integer face counts per direction (exact, order independent).
@@ -408,32 +517,43 @@ hipError_t launch_count_flags(const KGrid& g, const unsigned char* fx, const uns
     return hipGetLastError();
 }
 
-hipError_t launch_sensor_flags(const KGrid& g, const KScheme& sc, const double* W, double* theta,
-                               unsigned char* fx, unsigned char* fy, unsigned char* fz,
-                               int use_override, int* list, int* count, hipStream_t st)
+hipError_t launch_sensor_flags(const KGrid& g, const KScheme& sc, const double* W,
+                               const WenoBufs& b, int use_override, hipStream_t st)
 {
     const dim3 grid((unsigned)((g.nint + WB - 1) / WB));
-    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, st, count);
-    if (!use_override)
-        hipLaunchKernelGGL(k_theta, grid, dim3(WB), 0, st, g, sc.sensor_eps, W, theta);
-    hipLaunchKernelGGL(k_flags, grid, dim3(WB), 0, st, g, sc.r, sc.sensor_thr, theta, fx, fy, fz,
-                       use_override, list, count);
+    hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(64), 0, st, b.counts);
+    if (!use_override) {
+        hipLaunchKernelGGL(k_theta, grid, dim3(WB), 0, st, g, sc.sensor_eps, W, b.theta);
+        hipLaunchKernelGGL(k_flags, grid, dim3(WB), 0, st, g, sc.r, sc.sensor_thr, b.theta, b);
+    }
+    const long long per = (long long)WB * LPT;
+    hipLaunchKernelGGL(k_lists, dim3((unsigned)((g.nint + per - 1) / per)), dim3(WB), 0, st, g, b);
     return hipGetLastError();
 }
 
-// The grid of the correction kernel covers every node; threads past the
-// (device-side) list length return at once.
+// Face pass over the flagged faces of the directions in `mask`, then the
+// node pass over the listed nodes (persistent grids; list lengths stay on
+// the device).
 hipError_t launch_weno(const KGrid& g, const KGas& gas, const KScheme& sc, unsigned mask,
-                       const double* W, const unsigned char* fx, const unsigned char* fy,
-                       const unsigned char* fz, const int* list, const int* count, int mode,
-                       double cg, int write_prev, double* out, double* Rp, hipStream_t st)
+                       const double* W, const WenoBufs& b, int mode, double cg, int write_prev,
+                       double* out, double* Rp, hipStream_t st)
 {
+    hipError_t e;
+    const bool f32 = sc.precision == SX_FP32_FLUX;
     switch (sc.L) {
-    case 1: return launch_weno_L<1>(sc.r, g, gas, sc.weno_eps, mask, W, fx, fy, fz, list, count, mode, cg, write_prev, out, Rp, st);
-    case 2: return launch_weno_L<2>(sc.r, g, gas, sc.weno_eps, mask, W, fx, fy, fz, list, count, mode, cg, write_prev, out, Rp, st);
-    case 3: return launch_weno_L<3>(sc.r, g, gas, sc.weno_eps, mask, W, fx, fy, fz, list, count, mode, cg, write_prev, out, Rp, st);
-    default: return launch_weno_L<4>(sc.r, g, gas, sc.weno_eps, mask, W, fx, fy, fz, list, count, mode, cg, write_prev, out, Rp, st);
+    case 1: e = f32 ? launch_faces_L<1, float>(sc.r, g, gas, sc.weno_eps, mask, W, b, st)
+                    : launch_faces_L<1, double>(sc.r, g, gas, sc.weno_eps, mask, W, b, st); break;
+    case 2: e = f32 ? launch_faces_L<2, float>(sc.r, g, gas, sc.weno_eps, mask, W, b, st)
+                    : launch_faces_L<2, double>(sc.r, g, gas, sc.weno_eps, mask, W, b, st); break;
+    case 3: e = f32 ? launch_faces_L<3, float>(sc.r, g, gas, sc.weno_eps, mask, W, b, st)
+                    : launch_faces_L<3, double>(sc.r, g, gas, sc.weno_eps, mask, W, b, st); break;
+    default: e = f32 ? launch_faces_L<4, float>(sc.r, g, gas, sc.weno_eps, mask, W, b, st)
+                     : launch_faces_L<4, double>(sc.r, g, gas, sc.weno_eps, mask, W, b, st); break;
     }
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_weno_node, dim3(persistent_blocks()), dim3(WB), 0, st, g, mask, b, mode, cg,
+                       write_prev, out, Rp);
+    return hipGetLastError();
 }
 
 }  // namespace sx
