@@ -293,7 +293,7 @@ def main():
     avg_launch_s = kern_ms / launches * 1e-3
     alg_bytes_launch = ALG_BYTES_PER_POINT_STEP / SUBSTEPS * case.points
     achieved = alg_bytes_launch / avg_launch_s / 1e9
-    kernel = "k_rhs_central<3, 32, 8, 1, double, true, false>"
+    kernel = "k_rhs_central<3, 32, 8, 2, double, true, false, true>"
     traffic = load_traffic(kernel)
     line = {
         "metric": "grid-point updates/s per RK3 step (FP64 vs FP32-flux) + % HBM roofline",

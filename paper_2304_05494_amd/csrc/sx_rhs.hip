@@ -21,6 +21,15 @@
 // traffic of a substep is one read of W and Rprev, one write of W' and
 // Rprev.
 //
+// FP64 splits the work of a column between two waves (march_split): one
+// holds the convective terms, the column ring and the update, the other the
+// arrival plane, the mixed-derivative queues and the viscous terms, and
+// passes its part of the RHS through LDS. Each wave then needs under 256
+// registers, so every SIMD runs two waves whose instruction streams hide
+// each other's LDS and memory latencies (one wave of the unsplit FP64 march
+// needs ~390 registers and leaves the SIMD idle on every wait). FP32 halves
+// the registers and keeps the unsplit march at two waves per SIMD.
+//
 // Precision forms: R = double (FP64 path) or R = float (FP32-flux form:
 // primitives are computed in FP64 and converted once per node, pressure
 // and enthalpy shifted by constant reference values first; all stencil and
@@ -609,15 +618,400 @@ __device__ __forceinline__ void march(Smem<S, TX, TY, R>& sm, const double* __re
     flush();
 }
 
-template <int S, int TX, int TY, int WPE, typename R, bool UPD, bool PIMG>
-__global__ void __attribute__((amdgpu_flat_work_group_size(TX * TY, TX * TY), amdgpu_waves_per_eu(WPE)))
+// LDS working set of the role-split march: the non-split set plus the
+// viscous part of the RHS handed from the viscous to the convective role.
+template <int S, int TX, int TY, typename R>
+struct SmemSplit {
+    static constexpr int NR = TX * TY;
+    static constexpr int HX = TX + 2 * S, HY = TY + 2 * S, HP = HX * HY;
+    static constexpr int Q = 2 * S + 1;
+    R sa[3][HP];                                                    // arrival plane: u, v, w
+    __attribute__((aligned(16))) R so[Layout<R>::PREC * HP];        // output plane records
+    R sH[Layout<R>::SEP_H ? HP : 1];                                // output plane enthalpy
+    R gyl[2][TY][HX];                                               // D_y u, D_y v of plane k
+    __attribute__((aligned(16))) R zring[Q * NR * Layout<R>::ZREC]; // column records
+    R xch[NV][NR];                                                  // viscous RHS of plane k
+};
+
+// Role-split march: the workgroup holds two threads per tile column. Role 0
+// (the first TX*TY threads) stages the output plane and the column ring,
+// evaluates the convective terms and applies the update; role 1 stages the
+// arrival plane, keeps the mixed-derivative queues and evaluates the
+// viscous terms, which it passes to role 0 through LDS. Each wave has one
+// role, so the two halves run as separate instruction streams that the
+// SIMDs interleave, and each holds half the per-column state.
+template <int S, int TX, int TY, typename R, bool UPD, bool PIMG>
+__device__ __forceinline__ void march_split(SmemSplit<S, TX, TY, R>& sm, const double* __restrict__ W,
+                                            double* __restrict__ out, double* __restrict__ Rp,
+                                            const KGrid& g, const KGas& gas, const StepCoef& sc,
+                                            unsigned mask_in, int i0, int j0, int k0, int k1)
+{
+    const unsigned mask = UPD ? (unsigned)SX_ALL : mask_in;
+    using L = Layout<R>;
+    constexpr int NR = TX * TY;
+    constexpr int HX = TX + 2 * S, HP = HX * (TY + 2 * S);
+    constexpr int NPT = (HP + NR - 1) / NR;
+    constexpr int Q = 2 * S + 1;
+    static_assert(NR % 64 == 0, "each role fills whole waves");
+    static_assert(64 % TX == 0, "every row of the tile lies in one wave");
+    auto& sa = sm.sa;
+    R* const so = sm.so;
+    R* const sH = sm.sH;
+    auto& gyl = sm.gyl;
+    R* const zring = sm.zring;
+    auto& xch = sm.xch;
+
+    constexpr bool f32 = std::is_same<R, float>::value;
+    const double pref = f32 ? gas.pref : 0.0, href = f32 ? gas.href : 0.0;
+    const int role = threadIdx.x / NR;
+    const int tid = threadIdx.x - role * NR;
+    const int tx = tid % TX, ty = tid / TX;
+    const int i = i0 + tx, j = j0 + ty;
+    const bool active = i < g.nx && j < g.ny;
+    const int c = (ty + S) * HX + (tx + S);
+    const R ey = active ? R(g.eta_y[j]) : R(0);
+    const R eyy = active ? R(g.eta_yy[j]) : R(0);
+    const R dxi = R(g.dxi), dzi = R(g.dzi);
+    const R igM2 = R(gas.igM2);
+    const long long col = g.base + (long long)j * g.sy + i;
+    const bool visc = mask & SX_VISC;
+
+    auto halo_index = [&](int q, int k) -> long long {
+        const int hx = q % HX, hy = q / HX;
+        const int gi = i0 - S + hx, gj = j0 - S + hy;
+        if (q < HP && gi >= -g.ng && gi < g.nx + g.ng && gj >= -g.ng && gj < g.ny + g.ng)
+            return g.base + (long long)k * g.sz + (long long)gj * g.sy + gi;
+        return -1;
+    };
+    auto fetch = [&](PlaneFetch<NPT>& f, int k, int nvar) {
+#pragma unroll
+        for (int a = 0; a < NPT; ++a) {
+            const long long n = halo_index(tid + a * NR, k);
+            f.q[a][0] = 1.0;
+            f.q[a][1] = f.q[a][2] = f.q[a][3] = 0.0;
+            f.q[a][4] = 1.0;
+            if (n >= 0) {
+#pragma unroll
+                for (int v = 0; v < 5; ++v)
+                    if (v < nvar) f.q[a][v] = W[n + v * g.sv];
+            }
+        }
+    };
+    auto prims = [&](const double* w5, double& rho, double& u, double& v, double& w, double& T,
+                     double& p, double& H) {
+        rho = w5[0];
+        const double ri = rcp(rho);
+        u = w5[1] * ri;
+        v = w5[2] * ri;
+        w = w5[3] * ri;
+        const double pr = gas.gm1 * (w5[4] - 0.5 * rho * (u * u + v * v + w * w));
+        T = gas.gM2 * pr * ri;
+        H = (w5[4] + pr) * ri - href;
+        p = pr - pref;
+    };
+    auto znode = [&](int slot) { return ring_read<R>(zring + L::ZREC * (slot * NR + tid), igM2); };
+    auto getx = [&](int t) { return plane_read<R>(so, sH, c + t); };
+    auto gety = [&](int t) { return plane_read<R>(so, sH, c + t * HX); };
+
+    if (role == 0) {
+        // ---- convective terms, column ring, update ----------------------
+        auto fetch_col = [&](double (&cq)[5], int k) {
+            const long long n = col + (long long)k * g.sz;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) cq[v] = active ? W[n + v * g.sv] : (v == 0 ? 1.0 : 0.0);
+        };
+        double wc[5], rp[5];
+        auto fetch_centre = [&](int k) {
+            const long long n = col + (long long)k * g.sz;
+            const long long m = ((long long)k * g.ny + j) * g.nx + i;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) wc[v] = rp[v] = 0.0;
+            if (UPD && active) {
+#pragma unroll
+                for (int v = 0; v < 5; ++v) wc[v] = W[n + v * g.sv];
+                if (sc.read_prev) {
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) rp[v] = Rp[m + v * g.nint];
+                }
+            }
+        };
+        auto stage_output = [&](const PlaneFetch<NPT>& f) {
+#pragma unroll
+            for (int a = 0; a < NPT; ++a) {
+                const int q = tid + a * NR;
+                if (q < HP) {
+                    double rho, u, v, w, T, p, H;
+                    prims(f.q[a], rho, u, v, w, T, p, H);
+                    plane_write<R>(so, sH, q, rho, u, v, w, T, p, H);
+                }
+            }
+        };
+        auto stage_column = [&](int slot, const double (&cq)[5]) {
+            double rho, u, v, w, T, p, H;
+            prims(cq, rho, u, v, w, T, p, H);
+            ring_write<R>(zring + L::ZREC * (slot * NR + tid), rho, u, v, w, T, p, H);
+        };
+        PlaneFetch<NPT> fo;
+        double cq[5];
+        for (int t = 0; t < 2 * S; ++t) {
+            fetch_col(cq, k0 - S + t);
+            stage_column(t, cq);
+            __syncthreads();
+            __syncthreads();
+        }
+        fetch(fo, k0, 5);
+        fetch_col(cq, k0 + S);
+        fetch_centre(k0);
+
+        double pend[NV] = {0, 0, 0, 0, 0};
+        double pend_w[NV] = {0, 0, 0, 0, 0};
+        long long pend_n = -1, pend_m = -1;
+        auto flush = [&]() {
+            if (pend_n < 0) return;
+            if (UPD) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) out[v * g.sv + pend_n] = pend_w[v];
+                if constexpr (PIMG) {
+                    const int kk = (int)((pend_n - col) / g.sz);
+                    const int ox = i < g.ng ? g.nx : (i >= g.nx - g.ng ? -g.nx : 0);
+                    const int oy = j < g.ng ? g.ny : (j >= g.ny - g.ng ? -g.ny : 0);
+                    const int oz = kk < g.ng ? g.nz : (kk >= g.nz - g.ng ? -g.nz : 0);
+                    for (int c3 = 1; c3 < 8; ++c3) {
+                        const int dx = (c3 & 1) ? ox : 0, dy = (c3 & 2) ? oy : 0, dz = (c3 & 4) ? oz : 0;
+                        if (((c3 & 1) && !ox) || ((c3 & 2) && !oy) || ((c3 & 4) && !oz)) continue;
+                        const long long e = pend_n + dx + (long long)dy * g.sy + (long long)dz * g.sz;
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) out[v * g.sv + e] = pend_w[v];
+                    }
+                }
+                if (sc.write_prev) {
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) Rp[v * g.nint + pend_m] = pend[v];
+                }
+            } else {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) out[v * g.nint + pend_m] = pend[v];
+            }
+            pend_n = -1;
+        };
+
+        int slot_k = S;
+        for (int k = k0; k < k1; ++k) {
+            const int slot_new = slot_k + S >= Q ? slot_k + S - Q : slot_k + S;
+            stage_output(fo);
+            stage_column(slot_new, cq);
+            double wcur[5], rcur[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                wcur[v] = wc[v];
+                rcur[v] = rp[v];
+            }
+            flush();
+            __syncthreads();                                   // 1: planes staged
+            if (k + 1 < k1) {
+                fetch(fo, k + 1, 5);
+                fetch_col(cq, k + 1 + S);
+                fetch_centre(k + 1);
+            }
+            sched_fence();
+            R acc[NV] = {0, 0, 0, 0, 0};
+            if (active) {
+                R gd[4], dd[4];
+                auto getz = [&](int t) {
+                    int sl = slot_k + t;
+                    sl = sl < 0 ? sl + Q : (sl >= Q ? sl - Q : sl);
+                    return znode(sl);
+                };
+                if (mask & SX_CONV_X) stencil_dir<S, 0, true, false>(getx, dxi, dxi, R(0), acc, gd, dd);
+                if (mask & SX_CONV_Y) stencil_dir<S, 1, true, false>(gety, ey, ey, R(0), acc, gd, dd);
+                if (mask & SX_CONV_Z) stencil_dir<S, 2, true, false>(getz, dzi, dzi, R(0), acc, gd, dd);
+            }
+            __syncthreads();                                   // 2: viscous part ready
+            if (active) {
+                // enthalpy shift correction of the convective energy flux (FP64)
+                const double accE_shift = href * double(acc[0]);
+                pend_m = ((long long)k * g.ny + j) * g.nx + i;
+                pend_n = col + (long long)k * g.sz;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    double r = double(acc[v] + xch[v][tid]);
+                    if (f32 && v == 4) r += accE_shift;
+                    pend[v] = r;
+                    if (UPD) {
+                        double nv = __builtin_fma(sc.cg, r, wcur[v]);
+                        if (sc.read_prev) nv = __builtin_fma(sc.cz, rcur[v], nv);
+                        pend_w[v] = nv;
+                    }
+                }
+            }
+            slot_k = slot_k + 1 == Q ? 0 : slot_k + 1;
+            __syncthreads();                                   // 3: planes consumed
+        }
+        flush();
+    } else {
+        // ---- arrival plane, mixed-derivative queues, viscous terms -------
+        const R eyr = j < g.ny ? R(g.eta_y[j]) : R(0);
+        R m0[Q], m1[Q], m2[Q];   // D_x w, D_y w, D_x u + D_y v of this column
+#pragma unroll
+        for (int t = 0; t < Q; ++t) m0[t] = m1[t] = m2[t] = R(0);
+        auto stage_arrival = [&](const PlaneFetch<NPT>& f) {
+#pragma unroll
+            for (int a = 0; a < NPT; ++a) {
+                const int q = tid + a * NR;
+                if (q < HP) {
+                    const double ri = rcp(f.q[a][0]);
+                    sa[0][q] = R(f.q[a][1] * ri);
+                    sa[1][q] = R(f.q[a][2] * ri);
+                    sa[2][q] = R(f.q[a][3] * ri);
+                }
+            }
+        };
+        auto arrive = [&]() {
+            if (!active) return;
+            R xw[Q], yw[Q], xu[Q], yv[Q];
+#pragma unroll
+            for (int t = 0; t < Q; ++t) {
+                xu[t] = sa[0][c + t - S];
+                xw[t] = sa[2][c + t - S];
+                yv[t] = sa[1][c + (t - S) * HX];
+                yw[t] = sa[2][c + (t - S) * HX];
+            }
+            m0[Q - 1] = dxi * d1<S>(xw);
+            m1[Q - 1] = ey * d1<S>(yw);
+            m2[Q - 1] = dxi * d1<S>(xu) + ey * d1<S>(yv);
+        };
+        auto shift = [&]() {
+#pragma unroll
+            for (int t = 0; t < Q - 1; ++t) {
+                m0[t] = m0[t + 1];
+                m1[t] = m1[t + 1];
+                m2[t] = m2[t + 1];
+            }
+        };
+        PlaneFetch<NPT> fa;
+        for (int t = 0; t < 2 * S; ++t) {
+            fetch(fa, k0 - S + t, 4);
+            stage_arrival(fa);
+            __syncthreads();
+            arrive();
+            shift();
+            __syncthreads();
+        }
+        fetch(fa, k0 + S, 4);
+
+        int slot_k = S;
+        for (int k = k0; k < k1; ++k) {
+            stage_arrival(fa);
+            __syncthreads();                                   // 1: planes staged
+            arrive();
+            if (k + 1 < k1) fetch(fa, k + 1 + S, 4);
+            sched_fence();
+            // D_y u, D_y v over the x-extended columns of this thread's row;
+            // only this wave reads them (wavefront-scope ordering)
+            auto gy_at = [&](int hx) {
+                R su = 0, sv = 0;
+#pragma unroll
+                for (int l = 1; l <= S; ++l) {
+                    const int up = L::PREC * ((ty + S + l) * HX + hx), dn = L::PREC * ((ty + S - l) * HX + hx);
+                    su += R(Coef<S>::a[l]) * (so[up + 1] - so[dn + 1]);
+                    sv += R(Coef<S>::a[l]) * (so[up + 2] - so[dn + 2]);
+                }
+                gyl[0][ty][hx] = eyr * su;
+                gyl[1][ty][hx] = eyr * sv;
+            };
+            if (visc && j < g.ny) {
+                gy_at(tx + S);
+                if (tx < 2 * S) gy_at(tx < S ? tx : TX + tx);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            R acc[NV] = {0, 0, 0, 0, 0};
+            if (active && visc) {
+                const Node<R> Cz = znode(slot_k);
+                const R uc = Cz.u, vc = Cz.v, wc_ = Cz.w, Tc = Cz.T;
+                const R mu = visc_pow<R>(Tc, gas) * R(gas.ire);
+                const R kcd = mu * R(gas.cp * gas.ipr);
+                const R smt = R(gas.s) * rcpr<R>(Tc);
+                R gx[4], gy[4], gz[4], dd[4];
+                auto getz = [&](int t) {
+                    int sl = slot_k + t;
+                    sl = sl < 0 ? sl + Q : (sl >= Q ? sl - Q : sl);
+                    return znode(sl);
+                };
+                stencil_dir<S, 0, false, true>(getx, dxi, dxi * dxi, R(0), acc, gx, dd);
+                visc_linear<0>(dd, mu, kcd, uc, vc, wc_, acc);
+                stencil_dir<S, 1, false, true>(gety, ey, ey * ey, eyy, acc, gy, dd);
+                visc_linear<1>(dd, mu, kcd, uc, vc, wc_, acc);
+                stencil_dir<S, 2, false, true>(getz, dzi, dzi * dzi, R(0), acc, gz, dd);
+                visc_linear<2>(dd, mu, kcd, uc, vc, wc_, acc);
+                // mixed parts of mu/3 d_i(div u): d_x d_y, d_x d_z, d_y d_z
+                R gyu[Q], gyv[Q];
+#pragma unroll
+                for (int t = 0; t < Q; ++t) {
+                    gyu[t] = gyl[0][ty][tx + t];
+                    gyv[t] = gyl[1][ty][tx + t];
+                }
+                const R m3 = mu * R(1.0 / 3.0);
+                const R mx = m3 * (dxi * d1<S>(gyv) + dzi * d1<S>(m0));
+                const R my = m3 * (dxi * d1<S>(gyu) + dzi * d1<S>(m1));
+                const R mz = m3 * (dzi * d1<S>(m2));
+                acc[1] += mx;
+                acc[2] += my;
+                acc[3] += mz;
+                acc[4] += uc * mx + vc * my + wc_ * mz;
+                // nonlinear parts: grad mu (= s mu/T grad T) terms and dissipation
+                const R g00 = gx[0], g10 = gx[1], g20 = gx[2], Tx = gx[3];
+                const R g01 = gy[0], g11 = gy[1], g21 = gy[2], Ty = gy[3];
+                const R g02 = gz[0], g12 = gz[1], g22 = gz[2], Tz = gz[3];
+                const R th = g00 + g11 + g22;
+                const R smu = smt * mu;
+                const R dmu0 = smu * Tx, dmu1 = smu * Ty, dmu2 = smu * Tz;
+                const R t3 = R(2.0 / 3.0);
+                const R s01 = g01 + g10, s02 = g02 + g20, s12 = g12 + g21;
+                const R N0 = dmu0 * (R(2) * g00 - t3 * th) + dmu1 * s01 + dmu2 * s02;
+                const R N1 = dmu0 * s01 + dmu1 * (R(2) * g11 - t3 * th) + dmu2 * s12;
+                const R N2 = dmu0 * s02 + dmu1 * s12 + dmu2 * (R(2) * g22 - t3 * th);
+                const R diss = mu * ((R(2) * g00 - t3 * th) * g00 + (R(2) * g11 - t3 * th) * g11 +
+                                     (R(2) * g22 - t3 * th) * g22 + s01 * s01 + s02 * s02 + s12 * s12);
+                acc[1] += N0;
+                acc[2] += N1;
+                acc[3] += N2;
+                acc[4] += uc * N0 + vc * N1 + wc_ * N2 + diss + (smt * kcd) * (Tx * Tx + Ty * Ty + Tz * Tz);
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) xch[v][tid] = acc[v];
+            __syncthreads();                                   // 2: viscous part ready
+            shift();
+            slot_k = slot_k + 1 == Q ? 0 : slot_k + 1;
+            __syncthreads();                                   // 3: planes consumed
+        }
+    }
+}
+
+template <int S, int TX, int TY, typename R, bool SPLIT>
+struct SmemOf {
+    using type = Smem<S, TX, TY, R>;
+};
+template <int S, int TX, int TY, typename R>
+struct SmemOf<S, TX, TY, R, true> {
+    using type = SmemSplit<S, TX, TY, R>;
+};
+
+template <int S, int TX, int TY, int WPE, typename R, bool UPD, bool PIMG, bool SPLIT>
+__global__ void __attribute__((amdgpu_flat_work_group_size(TX * TY * (SPLIT ? 2 : 1), TX * TY * (SPLIT ? 2 : 1)),
+                               amdgpu_waves_per_eu(WPE)))
 k_rhs_central(const double* __restrict__ W, double* __restrict__ out, double* __restrict__ Rp,
               KGrid g, KGas gas, StepCoef sc, unsigned mask, int kc)
 {
-    __shared__ Smem<S, TX, TY, R> sm;
+    __shared__ typename SmemOf<S, TX, TY, R, SPLIT>::type sm;
     const int k0 = blockIdx.z * kc;
-    march<S, TX, TY, R, UPD, PIMG>(sm, W, out, Rp, g, gas, sc, mask, blockIdx.x * TX,
-                                   blockIdx.y * TY, k0, min(k0 + kc, g.nz));
+    if constexpr (SPLIT)
+        march_split<S, TX, TY, R, UPD, PIMG>(sm, W, out, Rp, g, gas, sc, mask, blockIdx.x * TX,
+                                             blockIdx.y * TY, k0, min(k0 + kc, g.nz));
+    else
+        march<S, TX, TY, R, UPD, PIMG>(sm, W, out, Rp, g, gas, sc, mask, blockIdx.x * TX,
+                                       blockIdx.y * TY, k0, min(k0 + kc, g.nz));
 }
 
 // Persistent batched kernel: each workgroup pulls (box, column tile,
@@ -625,14 +1019,15 @@ k_rhs_central(const double* __restrict__ W, double* __restrict__ out, double* __
 // The time step is read from device memory, so a captured launch stays
 // valid when dt changes; cg = dt gamma_k and cz = dt zeta_k are formed as on
 // the host path.
-template <int S, int TX, int TY, int WPE, typename R>
-__global__ void __attribute__((amdgpu_flat_work_group_size(TX * TY, TX * TY), amdgpu_waves_per_eu(WPE)))
+template <int S, int TX, int TY, int WPE, typename R, bool SPLIT>
+__global__ void __attribute__((amdgpu_flat_work_group_size(TX * TY * (SPLIT ? 2 : 1), TX * TY * (SPLIT ? 2 : 1)),
+                               amdgpu_waves_per_eu(WPE)))
 k_rhs_batch(const double* __restrict__ Wsrc, double* __restrict__ Wdst, double* __restrict__ Rp,
             const BoxDesc* __restrict__ boxes, const TileDesc* __restrict__ tiles, int ntiles,
             int* __restrict__ counter, const double* __restrict__ dtp, double gk, double zk,
             int substep)
 {
-    __shared__ Smem<S, TX, TY, R> sm;
+    __shared__ typename SmemOf<S, TX, TY, R, SPLIT>::type sm;
     __shared__ int cur;
     const double dt = *dtp;
     const StepCoef sc{dt * gk, dt * zk, substep > 0 ? 1 : 0, substep < 2 ? 1 : 0};
@@ -644,8 +1039,12 @@ k_rhs_batch(const double* __restrict__ Wsrc, double* __restrict__ Wdst, double* 
         if (t >= ntiles) break;
         const TileDesc td = tiles[t];
         const BoxDesc& bd = boxes[td.box];
-        march<S, TX, TY, R, true, true>(sm, Wsrc + bd.woff, Wdst + bd.woff, Rp + bd.roff, bd.g,
-                                        bd.gas, sc, (unsigned)SX_ALL, td.i0, td.j0, td.k0, td.k1);
+        if constexpr (SPLIT)
+            march_split<S, TX, TY, R, true, true>(sm, Wsrc + bd.woff, Wdst + bd.woff, Rp + bd.roff, bd.g,
+                                                  bd.gas, sc, (unsigned)SX_ALL, td.i0, td.j0, td.k0, td.k1);
+        else
+            march<S, TX, TY, R, true, true>(sm, Wsrc + bd.woff, Wdst + bd.woff, Rp + bd.roff, bd.g,
+                                            bd.gas, sc, (unsigned)SX_ALL, td.i0, td.j0, td.k0, td.k1);
         __syncthreads();
     }
 }
@@ -668,9 +1067,11 @@ __global__ void k_set_value(double* p, double v)
 template <typename R, int S>
 struct Tile {
     static constexpr bool F32 = std::is_same<R, float>::value;
+    static constexpr bool SPLIT = !F32;
     static constexpr int TX = (!F32 && S <= 3) ? 32 : 64;
     static constexpr int TY = F32 ? (S <= 3 ? 8 : 4) : (S <= 3 ? 8 : 2);
-    static constexpr int WPE = F32 ? 2 : 1;
+    static constexpr int NTH = TX * TY * (SPLIT ? 2 : 1);
+    static constexpr int WPE = F32 ? 2 : (SPLIT ? 2 : 1);
 };
 
 template <int S, typename R>
@@ -679,17 +1080,19 @@ static hipError_t launch_rhs_SR(const KGrid& g, const KGas& gas, const double* W
                                 hipStream_t st)
 {
     constexpr int TX = Tile<R, S>::TX, TY = Tile<R, S>::TY, WPE = Tile<R, S>::WPE;
+    constexpr bool SP = Tile<R, S>::SPLIT;
+    constexpr int NTH = Tile<R, S>::NTH;
     const int kc = g.nz;  // one march over the whole z extent per tile
     dim3 grid((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY, (g.nz + kc - 1) / kc);
     if (step && pimg) {
-        hipLaunchKernelGGL((k_rhs_central<S, TX, TY, WPE, R, true, true>), grid, dim3(TX * TY), 0, st,
+        hipLaunchKernelGGL((k_rhs_central<S, TX, TY, WPE, R, true, true, SP>), grid, dim3(NTH), 0, st,
                            W, out, Rprev, g, gas, *step, (unsigned)SX_ALL, kc);
     } else if (step) {
-        hipLaunchKernelGGL((k_rhs_central<S, TX, TY, WPE, R, true, false>), grid, dim3(TX * TY), 0, st,
+        hipLaunchKernelGGL((k_rhs_central<S, TX, TY, WPE, R, true, false, SP>), grid, dim3(NTH), 0, st,
                            W, out, Rprev, g, gas, *step, (unsigned)SX_ALL, kc);
     } else {
         StepCoef none{0.0, 0.0, 0, 0};
-        hipLaunchKernelGGL((k_rhs_central<S, TX, TY, WPE, R, false, false>), grid, dim3(TX * TY), 0,
+        hipLaunchKernelGGL((k_rhs_central<S, TX, TY, WPE, R, false, false, SP>), grid, dim3(NTH), 0,
                            st, W, out, Rprev, g, gas, none, mask, kc);
     }
     return hipGetLastError();
@@ -727,14 +1130,17 @@ struct BTile {
     static constexpr int TX = V == 0 ? 64 : 32;
     static constexpr int TY = NT / TX;
     static constexpr int WPE = Tile<R, S>::WPE;
+    static constexpr bool SPLIT = Tile<R, S>::SPLIT;
+    static constexpr int NTH = Tile<R, S>::NTH;
 };
 
 template <int S, typename R, int V>
 static hipError_t launch_batch_SRV(const BatchLaunch& b, hipStream_t st)
 {
     constexpr int TX = BTile<R, S, V>::TX, TY = BTile<R, S, V>::TY, WPE = BTile<R, S, V>::WPE;
+    constexpr bool SP = BTile<R, S, V>::SPLIT;
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, b.counter);
-    hipLaunchKernelGGL((k_rhs_batch<S, TX, TY, WPE, R>), dim3(b.nwg), dim3(TX * TY), 0, st, b.Wsrc,
+    hipLaunchKernelGGL((k_rhs_batch<S, TX, TY, WPE, R, SP>), dim3(b.nwg), dim3(BTile<R, S, V>::NTH), 0, st, b.Wsrc,
                        b.Wdst, b.Rp, b.boxes, b.tiles, b.ntiles, b.counter, b.dt, b.gk, b.zk,
                        b.substep);
     return hipGetLastError();
@@ -744,8 +1150,9 @@ template <int S, typename R, int V>
 static int occupancy_SRV()
 {
     constexpr int TX = BTile<R, S, V>::TX, TY = BTile<R, S, V>::TY, WPE = BTile<R, S, V>::WPE;
+    constexpr bool SP = BTile<R, S, V>::SPLIT;
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rhs_batch<S, TX, TY, WPE, R>, TX * TY, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rhs_batch<S, TX, TY, WPE, R, SP>, BTile<R, S, V>::NTH, 0) !=
         hipSuccess)
         return 0;
     return nb;
