@@ -93,23 +93,26 @@ struct Node {
     R r, u, v, w, T, p, H;
 };
 
-// LDS record layouts. FP64: plane records of 6 doubles (read as three
-// 128-bit loads; the 48-byte stride is bank-conflict free) plus a separate
-// enthalpy array; ring records (rho,u,v,w,T,H) with p derived. FP32: 7-float
-// records (rho,u,v,w,T,p',H') read as 32-bit loads (stride 7 is coprime
-// with the 64 banks).
+// LDS record layouts. FP64: plane records of 6 doubles read as three 128-bit
+// loads, ordered (u, v | w, T | rho, p) so the viscous terms, which need u,
+// v, w, T only, read the first two; the enthalpy in a separate array. Ring
+// records (u, v | w, T | rho, H), p derived. (The 48-byte stride is bank
+// conflict free.) FP32: 7-float records (rho, u, v, w, T, p', H') read as
+// 32-bit loads (stride 7 is coprime with the 64 banks).
 template <typename R>
 struct Layout;
 template <>
 struct Layout<double> {
     static constexpr int PREC = 6;   // plane record
     static constexpr int ZREC = 6;   // ring record
+    static constexpr int OU = 0, OV = 1;   // offsets of u and v in a plane record
     static constexpr bool SEP_H = true;
 };
 template <>
 struct Layout<float> {
     static constexpr int PREC = 7;
     static constexpr int ZREC = 7;
+    static constexpr int OU = 1, OV = 2;
     static constexpr bool SEP_H = false;
 };
 
@@ -119,9 +122,9 @@ __device__ __forceinline__ void plane_write(R* so, R* sH, int q, double rho, dou
 {
     if constexpr (std::is_same<R, double>::value) {
         double2* rec = reinterpret_cast<double2*>(so + 6 * q);
-        rec[0] = make_double2(rho, u);
-        rec[1] = make_double2(v, w);
-        rec[2] = make_double2(T, p);
+        rec[0] = make_double2(u, v);
+        rec[1] = make_double2(w, T);
+        rec[2] = make_double2(rho, p);
         sH[q] = H;
     } else {
         R* rec = so + 7 * q;
@@ -136,7 +139,7 @@ __device__ __forceinline__ Node<R> plane_read(const R* so, const R* sH, int q)
     if constexpr (std::is_same<R, double>::value) {
         const double2* rec = reinterpret_cast<const double2*>(so + 6 * q);
         const double2 a = rec[0], b = rec[1], e = rec[2];
-        return Node<double>{a.x, a.y, b.x, b.y, e.x, e.y, sH[q]};
+        return Node<double>{e.x, a.x, a.y, b.x, b.y, e.y, sH[q]};
     } else {
         const R* rec = so + 7 * q;
         return Node<R>{rec[0], rec[1], rec[2], rec[3], rec[4], rec[5], rec[6]};
@@ -149,9 +152,9 @@ __device__ __forceinline__ void ring_write(R* z, double rho, double u, double v,
 {
     if constexpr (std::is_same<R, double>::value) {
         double2* rec = reinterpret_cast<double2*>(z);
-        rec[0] = make_double2(rho, u);
-        rec[1] = make_double2(v, w);
-        rec[2] = make_double2(T, H);
+        rec[0] = make_double2(u, v);
+        rec[1] = make_double2(w, T);
+        rec[2] = make_double2(rho, H);
         (void)p;
     } else {
         z[0] = R(rho); z[1] = R(u); z[2] = R(v); z[3] = R(w); z[4] = R(T); z[5] = R(p); z[6] = R(H);
@@ -164,7 +167,7 @@ __device__ __forceinline__ Node<R> ring_read(const R* z, R igM2)
     if constexpr (std::is_same<R, double>::value) {
         const double2* rec = reinterpret_cast<const double2*>(z);
         const double2 a = rec[0], b = rec[1], e = rec[2];
-        return Node<double>{a.x, a.y, b.x, b.y, e.x, a.x * e.x * igM2, e.y};
+        return Node<double>{e.x, a.x, a.y, b.x, b.y, e.x * b.y * igM2, e.y};
     } else {
         return Node<R>{z[0], z[1], z[2], z[3], z[4], z[5], z[6]};
     }
@@ -506,8 +509,8 @@ __device__ __forceinline__ void march(Smem<S, TX, TY, R>& sm, const double* __re
 #pragma unroll
             for (int l = 1; l <= S; ++l) {
                 const int up = L::PREC * ((ty + S + l) * HX + hx), dn = L::PREC * ((ty + S - l) * HX + hx);
-                su += R(Coef<S>::a[l]) * (so[up + 1] - so[dn + 1]);
-                sv += R(Coef<S>::a[l]) * (so[up + 2] - so[dn + 2]);
+                su += R(Coef<S>::a[l]) * (so[up + L::OU] - so[dn + L::OU]);
+                sv += R(Coef<S>::a[l]) * (so[up + L::OV] - so[dn + L::OV]);
             }
             gyl[0][ty][hx] = eyr * su;
             gyl[1][ty][hx] = eyr * sv;
@@ -913,8 +916,8 @@ __device__ __forceinline__ void march_split(SmemSplit<S, TX, TY, R>& sm, const d
 #pragma unroll
                 for (int l = 1; l <= S; ++l) {
                     const int up = L::PREC * ((ty + S + l) * HX + hx), dn = L::PREC * ((ty + S - l) * HX + hx);
-                    su += R(Coef<S>::a[l]) * (so[up + 1] - so[dn + 1]);
-                    sv += R(Coef<S>::a[l]) * (so[up + 2] - so[dn + 2]);
+                    su += R(Coef<S>::a[l]) * (so[up + L::OU] - so[dn + L::OU]);
+                    sv += R(Coef<S>::a[l]) * (so[up + L::OV] - so[dn + L::OV]);
                 }
                 gyl[0][ty][hx] = eyr * su;
                 gyl[1][ty][hx] = eyr * sv;
