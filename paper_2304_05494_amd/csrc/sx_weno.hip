@@ -82,40 +82,77 @@ __global__ void __launch_bounds__(WB) k_theta(KGrid g, double eps, const double*
 
 // Face flags: f[d] holds n_d + 1 faces per line (entry f is the face
 // between nodes f-1 and f). Node (i, j, k) decides the face after it along
-// each direction and, for i = 0 (j = 0, k = 0), the first face of its line.
-__global__ void __launch_bounds__(WB) k_flags(KGrid g, int r, double thr,
-                                              const double* __restrict__ theta, WenoBufs b)
+// each direction and, for i = 0 (j = 0, k = 0), the first face of its line:
+// flagged iff the largest theta over the 2r nodes of the face's stencil
+// exceeds the threshold. A workgroup owns an FX x FY column tile and
+// marches a chunk of FZ planes: theta of the plane with an r-wide x/y halo
+// sits in LDS (x and y maxima), each thread keeps its column's last 2r
+// theta values in registers (z maxima).
+constexpr int FX = 64, FY = 4, RMAX = 4, FZ = 16;   // tile and z-chunk of k_flags
+__global__ void __launch_bounds__(FX * FY) k_flags(KGrid g, int r, double thr,
+                                                   const double* __restrict__ theta, WenoBufs b)
 {
-    const long long m = (long long)blockIdx.x * WB + threadIdx.x;
-    if (m >= g.nint) return;
-    const int i = (int)(m % g.nx);
-    const long long jk = m / g.nx;
-    const int j = (int)(jk % g.ny);
-    const int k = (int)(jk / g.ny);
+    constexpr int HXF = FX + 2 * RMAX, HYF = FY + 2 * RMAX;
+    __shared__ double pl[HYF][HXF];
+    const int tx = threadIdx.x % FX, ty = threadIdx.x / FX;
+    const int i0 = blockIdx.x * FX, j0 = blockIdx.y * FY;
+    const int i = i0 + tx, j = j0 + ty;
+    const bool active = i < g.nx && j < g.ny;
     auto th = [&](int a, int bb, int c) -> double {
         const int ia = map_ghost(a, g.nx, g.bc[0], g.bc[1]);
         const int jb = map_ghost(bb, g.ny, g.bc[2], g.bc[3]);
         const int kc = map_ghost(c, g.nz, g.bc[4], g.bc[5]);
         return theta[((long long)kc * g.ny + jb) * g.nx + ia];
     };
-    // flag of the face after node (a,bb,c) along d
-    auto face = [&](int d, int a, int bb, int c) -> unsigned char {
+    const int ic = active ? i : 0, jc = active ? j : 0;
+    const int k0 = blockIdx.z * FZ, k1 = min(k0 + FZ, g.nz);
+    double win[2 * RMAX];   // theta of this column at planes k-r+1 .. k+r
+#pragma unroll
+    for (int t = 0; t < 2 * RMAX; ++t) win[t] = 0.0;
+    for (int t = 0; t < 2 * r; ++t) win[t] = th(ic, jc, k0 - r + t);   // planes k0-r .. k0+r-1
+    const long long sfz = (long long)g.ny * g.nx;
+    if (active && k0 == 0) {
         double mx = 0.0;
-        for (int t = -r + 1; t <= r; ++t) {
-            const double v = d == 0 ? th(a + t, bb, c) : (d == 1 ? th(a, bb + t, c) : th(a, bb, c + t));
-            mx = v > mx ? v : mx;
+        for (int t = 0; t < 2 * r; ++t) mx = win[t] > mx ? win[t] : mx;
+        b.f[2][(long long)j * g.nx + i] = mx > thr ? 1 : 0;        // face -1/2 of the z line
+    }
+    for (int k = k0; k < k1; ++k) {
+        // shift the window to planes k-r+1 .. k+r
+        for (int t = 0; t < 2 * r - 1; ++t) win[t] = win[t + 1];
+        win[2 * r - 1] = th(ic, jc, k + r);
+        __syncthreads();
+        for (int q = threadIdx.x; q < HXF * HYF; q += FX * FY) {
+            const int hx = q % HXF, hy = q / HXF;
+            const int a = i0 - RMAX + hx, bb = j0 - RMAX + hy;
+            // only the r-wide halo is read (and mapped: r <= ghost width <= n)
+            pl[hy][hx] = (a >= -r && a < g.nx + r && bb >= -r && bb < g.ny + r) ? th(a, bb, k) : 0.0;
         }
-        return mx > thr ? 1 : 0;
-    };
-    const long long ix = ((long long)k * g.ny + j) * (g.nx + 1) + i;       // face i-1/2 in fx
-    const long long iy = ((long long)k * (g.ny + 1) + j) * g.nx + i;       // face j-1/2 in fy
-    const long long iz = ((long long)k * g.ny + j) * g.nx + i;             // face k-1/2 in fz
-    b.f[0][ix + 1] = face(0, i, j, k);
-    b.f[1][iy + g.nx] = face(1, i, j, k);
-    b.f[2][iz + (long long)g.ny * g.nx] = face(2, i, j, k);
-    if (i == 0) b.f[0][ix] = face(0, i - 1, j, k);
-    if (j == 0) b.f[1][iy] = face(1, i, j - 1, k);
-    if (k == 0) b.f[2][iz] = face(2, i, j, k - 1);
+        __syncthreads();
+        if (!active) continue;
+        const int cx = tx + RMAX, cy = ty + RMAX;
+        double mx = 0.0, my = 0.0, mz = 0.0;
+        for (int t = -r + 1; t <= r; ++t) {
+            mx = fmax(mx, pl[cy][cx + t]);
+            my = fmax(my, pl[cy + t][cx]);
+        }
+        for (int t = 0; t < 2 * r; ++t) mz = fmax(mz, win[t]);
+        const long long ix = ((long long)k * g.ny + j) * (g.nx + 1) + i;
+        const long long iy = ((long long)k * (g.ny + 1) + j) * g.nx + i;
+        const long long iz = ((long long)k * g.ny + j) * g.nx + i;
+        b.f[0][ix + 1] = mx > thr ? 1 : 0;
+        b.f[1][iy + g.nx] = my > thr ? 1 : 0;
+        b.f[2][iz + sfz] = mz > thr ? 1 : 0;
+        if (i == 0) {   // face -1/2 of the x line: nodes -r .. r-1
+            double m0 = 0.0;
+            for (int t = -r; t <= r - 1; ++t) m0 = fmax(m0, pl[cy][cx + t]);
+            b.f[0][ix] = m0 > thr ? 1 : 0;
+        }
+        if (j == 0) {
+            double m0 = 0.0;
+            for (int t = -r; t <= r - 1; ++t) m0 = fmax(m0, pl[cy + t][cx]);
+            b.f[1][iy] = m0 > thr ? 1 : 0;
+        }
+    }
 }
 
 // Wave-aggregated append into a workgroup's LDS cursor: returns this lane's
@@ -524,7 +561,9 @@ hipError_t launch_sensor_flags(const KGrid& g, const KScheme& sc, const double* 
     hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(64), 0, st, b.counts);
     if (!use_override) {
         hipLaunchKernelGGL(k_theta, grid, dim3(WB), 0, st, g, sc.sensor_eps, W, b.theta);
-        hipLaunchKernelGGL(k_flags, grid, dim3(WB), 0, st, g, sc.r, sc.sensor_thr, b.theta, b);
+        const dim3 fgrid((unsigned)((g.nx + FX - 1) / FX), (unsigned)((g.ny + FY - 1) / FY),
+                         (unsigned)((g.nz + FZ - 1) / FZ));
+        hipLaunchKernelGGL(k_flags, fgrid, dim3(FX * FY), 0, st, g, sc.r, sc.sensor_thr, b.theta, b);
     }
     const long long per = (long long)WB * LPT;
     hipLaunchKernelGGL(k_lists, dim3((unsigned)((g.nint + per - 1) / per)), dim3(WB), 0, st, g, b);
