@@ -29,6 +29,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector
+FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector (packed; unpacked issue is half)
 # Algorithmic HBM bytes per interior point of one RK3 step: 3 reads + 3
 # writes of the 5 FP64 conserved variables, the RK register written in
 # substeps 1-2 and read in substeps 2-3 -> (6 + 4) * 40 B.
@@ -84,6 +86,21 @@ def load_traffic(kernel: str):
         if rec.get("kernel") != kernel or rec.get("source_sha256") != digest:
             return None
         return float(rec["bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def load_flops(kernel: str):
+    """Counter-measured VALU flops per launch (profiles/valu_flops.json), if
+    recorded for the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "valu_flops.json")
+    try:
+        import hashlib
+        rec = json.load(open(path))
+        src = os.path.join(ROOT, "paper_2304_05494_amd", "csrc", "sx_rhs.hip")
+        if rec.get("source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+            return None
+        return rec["kernels"].get(kernel)
     except Exception:
         return None
 
@@ -333,6 +350,13 @@ def main():
         "state_ok": ok,
         "wall_s_timed": wall,
     }
+    fl = load_flops(kernel)
+    if fl is not None:
+        tf = fl["fp64_flops_per_launch"] / avg_launch_s / 1e12
+        line["valu"] = {"bound": "alu", "achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": tf / FP64_PEAK_TFLOPS,
+                        "flops_per_launch": fl["fp64_flops_per_launch"],
+                        "source": "SQ_INSTS_VALU_*_F64 counters (profiles/valu_flops.json) / live launch time"}
     # the same workload in the FP32-flux precision form
     h32 = sx.Handle(case, precision=sx.SX_FP32_FLUX)
     W32 = h32.to_layout(Wn)
@@ -349,7 +373,9 @@ def main():
     torch.cuda.synchronize()
     ms32 = start.elapsed_time(stop) / args.steps
     n32, k32 = h32.sx_timing_read()
+    fl32 = load_flops("k_rhs_central<3, 64, 8, 2, float, true, false, false>")
     line["fp32_flux"] = {
+        "valu_fp32_tflops": None if fl32 is None else fl32["fp32_flops_per_launch"] / (k32 / n32 * 1e-3) / 1e12,
         "value": case.points / (ms32 * 1e-3),
         "ms_per_step": ms32,
         "speedup_vs_fp64": ms_per_step / ms32,
