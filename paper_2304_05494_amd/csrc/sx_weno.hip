@@ -46,38 +46,63 @@ __device__ __forceinline__ int map_ghost(int i, int n, int bc_lo, int bc_hi)
     return i;
 }
 
-// theta at interior nodes, stored [nz][ny][nx]
-__global__ void __launch_bounds__(WB) k_theta(KGrid g, double eps, const double* __restrict__ W,
-                                              double* __restrict__ theta)
+// theta at interior nodes, stored [nz][ny][nx]. A workgroup owns a TXT x
+// TYT column tile and marches a chunk of TZT planes; velocities of three
+// planes (tile + one halo node, read from the ghosted state) sit in an LDS
+// ring, so each node's velocity is formed once.
+constexpr int TXT = 64, TYT = 4, TZT = 16;
+__global__ void __launch_bounds__(TXT * TYT) k_theta(KGrid g, double eps, const double* __restrict__ W,
+                                                     double* __restrict__ theta)
 {
-    const long long m = (long long)blockIdx.x * WB + threadIdx.x;
-    if (m >= g.nint) return;
-    const int i = (int)(m % g.nx);
-    const long long jk = m / g.nx;
-    const int j = (int)(jk % g.ny);
-    const int k = (int)(jk / g.ny);
-    const long long n = g.base + (long long)k * g.sz + (long long)j * g.sy + i;
-    auto vel = [&](long long q, double& u, double& v, double& w) {
-        const double ri = 1.0 / W[q];
-        u = W[q + g.sv] * ri;
-        v = W[q + 2 * g.sv] * ri;
-        w = W[q + 3 * g.sv] * ri;
+    constexpr int HXT = TXT + 2, HYT = TYT + 2, HPT = HXT * HYT;
+    __shared__ double vel[3][3][HPT];   // ring slot, component, node
+    const int tx = threadIdx.x % TXT, ty = threadIdx.x / TXT;
+    const int i0 = blockIdx.x * TXT, j0 = blockIdx.y * TYT;
+    const int i = i0 + tx, j = j0 + ty;
+    const int k0 = blockIdx.z * TZT, k1 = min(k0 + TZT, g.nz);
+    const bool active = i < g.nx && j < g.ny;
+    auto stage = [&](int slot, int k) {
+        for (int q = threadIdx.x; q < HPT; q += TXT * TYT) {
+            const int a = i0 - 1 + q % HXT, bb = j0 - 1 + q / HXT;
+            double u = 0.0, v = 0.0, w = 0.0;
+            if (a < g.nx + g.ng && bb < g.ny + g.ng) {
+                const long long n = g.base + (long long)k * g.sz + (long long)bb * g.sy + a;
+                const double ri = 1.0 / W[n];
+                u = W[n + g.sv] * ri;
+                v = W[n + 2 * g.sv] * ri;
+                w = W[n + 3 * g.sv] * ri;
+            }
+            vel[slot][0][q] = u;
+            vel[slot][1][q] = v;
+            vel[slot][2][q] = w;
+        }
     };
-    double up, vp, wp, um, vm, wm;
-    const double ix = 0.5 * g.dxi, iy = 0.5 * g.eta_y[j], iz = 0.5 * g.dzi;
-    vel(n + 1, up, vp, wp);
-    vel(n - 1, um, vm, wm);
-    const double ux = (up - um) * ix, vx = (vp - vm) * ix, wx = (wp - wm) * ix;
-    vel(n + g.sy, up, vp, wp);
-    vel(n - g.sy, um, vm, wm);
-    const double uy = (up - um) * iy, vy = (vp - vm) * iy, wy = (wp - wm) * iy;
-    vel(n + g.sz, up, vp, wp);
-    vel(n - g.sz, um, vm, wm);
-    const double uz = (up - um) * iz, vz = (vp - vm) * iz, wz = (wp - wm) * iz;
-    const double div = ux + vy + wz;
-    const double o1 = wy - vz, o2 = uz - wx, o3 = vx - uy;
-    const double t = -div / sqrt(div * div + (o1 * o1 + o2 * o2 + o3 * o3) + eps * eps);
-    theta[m] = t > 0.0 ? t : 0.0;
+    stage(0, k0 - 1);
+    stage(1, k0);
+    const double ix = 0.5 * g.dxi, iz = 0.5 * g.dzi;
+    const double iy = active ? 0.5 * g.eta_y[j] : 0.0;
+    const int c = (ty + 1) * HXT + tx + 1;
+    for (int k = k0; k < k1; ++k) {
+        const int sm = (k - k0) % 3, s0 = (k - k0 + 1) % 3, sp = (k - k0 + 2) % 3;   // planes k-1, k, k+1
+        stage(sp, k + 1);
+        __syncthreads();
+        if (active) {
+            const double ux = (vel[s0][0][c + 1] - vel[s0][0][c - 1]) * ix;
+            const double vx = (vel[s0][1][c + 1] - vel[s0][1][c - 1]) * ix;
+            const double wx = (vel[s0][2][c + 1] - vel[s0][2][c - 1]) * ix;
+            const double uy = (vel[s0][0][c + HXT] - vel[s0][0][c - HXT]) * iy;
+            const double vy = (vel[s0][1][c + HXT] - vel[s0][1][c - HXT]) * iy;
+            const double wy = (vel[s0][2][c + HXT] - vel[s0][2][c - HXT]) * iy;
+            const double uz = (vel[sp][0][c] - vel[sm][0][c]) * iz;
+            const double vz = (vel[sp][1][c] - vel[sm][1][c]) * iz;
+            const double wz = (vel[sp][2][c] - vel[sm][2][c]) * iz;
+            const double div = ux + vy + wz;
+            const double o1 = wy - vz, o2 = uz - wx, o3 = vx - uy;
+            const double t = -div / sqrt(div * div + (o1 * o1 + o2 * o2 + o3 * o3) + eps * eps);
+            theta[((long long)k * g.ny + j) * g.nx + i] = t > 0.0 ? t : 0.0;
+        }
+        __syncthreads();
+    }
 }
 
 // Face flags: f[d] holds n_d + 1 faces per line (entry f is the face
@@ -560,7 +585,9 @@ hipError_t launch_sensor_flags(const KGrid& g, const KScheme& sc, const double* 
     const dim3 grid((unsigned)((g.nint + WB - 1) / WB));
     hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(64), 0, st, b.counts);
     if (!use_override) {
-        hipLaunchKernelGGL(k_theta, grid, dim3(WB), 0, st, g, sc.sensor_eps, W, b.theta);
+        const dim3 tgrid((unsigned)((g.nx + TXT - 1) / TXT), (unsigned)((g.ny + TYT - 1) / TYT),
+                         (unsigned)((g.nz + TZT - 1) / TZT));
+        hipLaunchKernelGGL(k_theta, tgrid, dim3(TXT * TYT), 0, st, g, sc.sensor_eps, W, b.theta);
         const dim3 fgrid((unsigned)((g.nx + FX - 1) / FX), (unsigned)((g.ny + FY - 1) / FY),
                          (unsigned)((g.nz + FZ - 1) / FZ));
         hipLaunchKernelGGL(k_flags, fgrid, dim3(FX * FY), 0, st, g, sc.r, sc.sensor_thr, b.theta, b);
