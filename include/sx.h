@@ -94,8 +94,9 @@ typedef struct {
     int weno_order;           /* 1, 3, 5 */
     int visc_order;           /* must equal central_order in this build */
     int sensor;               /* 0 off (pure central), 1 Ducros hybrid; the hybrid
-                                 allocates theta, face flags and a node list
-                                 (about 17 bytes per node) at sx_init */
+                                 allocates at sx_init the sensor, face flags,
+                                 face and node lists and the per-face WENO
+                                 flux differences: about 150 bytes per node */
     double sensor_thr;        /* WENO where max sensor over the stencil > thr */
     double sensor_eps;        /* epsilon of the sensor denominator */
     double weno_eps;          /* epsilon of the WENO weights */
@@ -130,9 +131,10 @@ typedef struct {
 typedef struct sx_handle sx_handle;
 
 /* Validates the description, computes the y metrics on the host (D1/D2 of
- * the node coordinates, central order) and uploads them. Allocates only
- * small library-owned device buffers (metrics, reduction scratch). On error
- * *out is NULL. */
+ * the node coordinates, central order) and uploads them. Allocates the
+ * library-owned device buffers: metrics and reduction scratch, plus the
+ * hybrid scheme's work arrays when the sensor is on (see sx_scheme). On
+ * error *out is NULL. */
 int sx_init(const sx_grid* grid, const sx_gas* gas, const sx_scheme* scheme,
             sx_handle** out);
 
