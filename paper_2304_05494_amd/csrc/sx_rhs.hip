@@ -1085,7 +1085,13 @@ static hipError_t launch_rhs_SR(const KGrid& g, const KGas& gas, const double* W
     constexpr int TX = Tile<R, S>::TX, TY = Tile<R, S>::TY, WPE = Tile<R, S>::WPE;
     constexpr bool SP = Tile<R, S>::SPLIT;
     constexpr int NTH = Tile<R, S>::NTH;
-    const int kc = g.nz;  // one march over the whole z extent per tile
+    // One march over the whole z extent per column tile, unless the block
+    // has too few tiles to fill the device: then z is cut into chunks (each
+    // chunk pays a 2S-plane prologue) until there are about 512 workgroups,
+    // keeping chunks of at least 8 planes.
+    const int ntiles = ((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY);
+    const int nch = max(1, min(512 / ntiles, g.nz / 8));
+    const int kc = (g.nz + nch - 1) / nch;
     dim3 grid((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY, (g.nz + kc - 1) / kc);
     if (step && pimg) {
         hipLaunchKernelGGL((k_rhs_central<S, TX, TY, WPE, R, true, true, SP>), grid, dim3(NTH), 0, st,
