@@ -343,6 +343,8 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": None if traffic is None else traffic,
+            # counter bytes (FETCH_SIZE x 2 + WRITE_SIZE, copy-calibrated) over the live launch time
+            "hw_frac": None if traffic is None else traffic / avg_launch_s / 1e9 / HBM_PEAK_GBS,
             "launch_ms": avg_launch_s * 1e3,
             "launches": launches,
             "alg_bytes_per_launch": alg_bytes_launch,
