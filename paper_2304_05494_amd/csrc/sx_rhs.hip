@@ -72,8 +72,60 @@ __device__ __forceinline__ R d1(const R (&f)[2 * S + 1])
 // base-2 logarithm and exponential.
 template <typename R>
 __device__ __forceinline__ R visc_pow(R T, const KGas& gas);
+// FP64 T^s = exp(s ln T) for T > 0 from two short series (relative error a
+// few ulp): ln m = 2 atanh z, z = (m-1)/(m+1), m in [1/sqrt2, sqrt2) (odd
+// series in z, |z| < 0.172, 12 terms), and exp r for |r| <= ln2/2 (Taylor,
+// 14 terms), with the exponents split off by frexp / ldexp and ln 2 carried
+// in two parts.
+__device__ __forceinline__ double visc_pow_f64(double T, double s)
+{
+    int e;
+    double m = frexp(T, &e);                       // T = m 2^e, m in [0.5, 1)
+    if (m < 0.70710678118654752440) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const double z = (m - 1.0) * rcp(m + 1.0);
+    const double z2 = z * z;
+    // atanh(z)/z = sum z^(2k) / (2k+1)
+    double q = 1.0 / 23.0;
+    q = __builtin_fma(q, z2, 1.0 / 21.0);
+    q = __builtin_fma(q, z2, 1.0 / 19.0);
+    q = __builtin_fma(q, z2, 1.0 / 17.0);
+    q = __builtin_fma(q, z2, 1.0 / 15.0);
+    q = __builtin_fma(q, z2, 1.0 / 13.0);
+    q = __builtin_fma(q, z2, 1.0 / 11.0);
+    q = __builtin_fma(q, z2, 1.0 / 9.0);
+    q = __builtin_fma(q, z2, 1.0 / 7.0);
+    q = __builtin_fma(q, z2, 1.0 / 5.0);
+    q = __builtin_fma(q, z2, 1.0 / 3.0);
+    const double lnm = 2.0 * __builtin_fma(z * z2, q, z);
+    constexpr double LN2_HI = 6.93147180369123816490e-01, LN2_LO = 1.90821492927058770002e-10;
+    // y = s ln T = s (e ln2 + ln m), ln2 in two parts
+    const double de = double(e);
+    const double y = s * __builtin_fma(de, LN2_HI, __builtin_fma(de, LN2_LO, lnm));
+    // exp(y) = 2^n exp(r), r = y - n ln2
+    const double n = rint(y * 1.44269504088896340736);
+    const double r = __builtin_fma(-n, LN2_LO, __builtin_fma(-n, LN2_HI, y));
+    double p = 1.0 / 87178291200.0;                // 1/14!
+    p = __builtin_fma(p, r, 1.0 / 6227020800.0);
+    p = __builtin_fma(p, r, 1.0 / 479001600.0);
+    p = __builtin_fma(p, r, 1.0 / 39916800.0);
+    p = __builtin_fma(p, r, 1.0 / 3628800.0);
+    p = __builtin_fma(p, r, 1.0 / 362880.0);
+    p = __builtin_fma(p, r, 1.0 / 40320.0);
+    p = __builtin_fma(p, r, 1.0 / 5040.0);
+    p = __builtin_fma(p, r, 1.0 / 720.0);
+    p = __builtin_fma(p, r, 1.0 / 120.0);
+    p = __builtin_fma(p, r, 1.0 / 24.0);
+    p = __builtin_fma(p, r, 1.0 / 6.0);
+    p = __builtin_fma(p, r, 0.5);
+    p = __builtin_fma(p, r, 1.0);
+    p = __builtin_fma(p, r, 1.0);
+    return ldexp(p, int(n));
+}
 template <>
-__device__ __forceinline__ double visc_pow<double>(double T, const KGas& gas) { return exp(gas.s * log(T)); }
+__device__ __forceinline__ double visc_pow<double>(double T, const KGas& gas) { return visc_pow_f64(T, gas.s); }
 template <>
 __device__ __forceinline__ float visc_pow<float>(float T, const KGas& gas)
 {
