@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form legs")
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the TGV, shock/boundary-layer and FP32-error legs")
+    ap.add_argument("--sweep", action="store_true",
+                    help="add the stencil-order sweep (channel, C2..C8, FP64 and FP32-flux) and "
+                         "the WENO-activation sweep (shock/boundary-layer block, injected flags)")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON autotune cache of the batched form (default: tune afresh)")
     return ap.parse_args()
@@ -188,6 +191,70 @@ def bench_shock_bl(args):
             out[name]["speedup_vs_fp64"] = ms64 / ms
         del h
         torch.cuda.empty_cache()
+    return out
+
+
+def bench_order_sweep(args, Wn, dt):
+    """The channel block at central/viscous orders 2, 4, 6, 8 in both
+    precision forms: RK3 step time, fused-kernel launch time and its
+    fraction of the HBM roofline (the algorithmic bytes do not depend on the
+    order; the arithmetic and the halo grow with it)."""
+    import numpy as np
+    import torch
+    from paper_2304_05494_amd import inputs, sx
+    out = {}
+    for order in (2, 4, 6, 8):
+        case = inputs.channel_case(central_order=order, visc_order=order)
+        # C8 needs four ghost layers: the same recipe on the wider ghosted array
+        Wo = Wn if case.ng == inputs.channel_case().ng else np.ascontiguousarray(inputs.fields(case))
+        row = {}
+        for prec, name in ((sx.SX_FP64, "fp64"), (sx.SX_FP32_FLUX, "fp32_flux")):
+            h = sx.Handle(case, prec)
+            h.sx_bind(h.to_layout(Wo))
+            ms, kms = time_steps(h, dt, args.steps, args.warmup)
+            d = h.sx_diagnostics()
+            row[name] = {"ms_per_step": ms, "launch_ms": kms,
+                         "roofline_frac": ALG_BYTES_PER_POINT_STEP / SUBSTEPS * case.points
+                         / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "state_ok": d.status == sx.SX_OK}
+            del h
+            torch.cuda.empty_cache()
+        out[f"C{order}V{order}"] = row
+    return out
+
+
+def bench_activation_sweep(args):
+    """The shock/boundary-layer block 1024x256x128 (FP64, W5 + C6 + V6) with
+    seeded random face flags injected at a given fraction of the faces of
+    every direction (the sensor pass is replaced by the injected flags):
+    RK3 step time against the WENO fraction."""
+    import numpy as np
+    import torch
+    from paper_2304_05494_amd import inputs, sx
+    case = inputs.shock_bl_case()
+    Wn = np.ascontiguousarray(inputs.fields(case))
+    nx, ny, nz = case.nx, case.ny, case.nz
+    out = {}
+    dt = None
+    for frac in (0.0, 0.05, 0.1, 0.25, 0.5, 1.0):
+        rng = np.random.Generator(np.random.PCG64(11))
+        flags = [(rng.random(shape, dtype=np.float32) < frac).astype(np.uint8)
+                 for shape in ((nz, ny, nx + 1), (nz, ny + 1, nx), (nz + 1, ny, nx))]
+        h = sx.Handle(case)
+        h.sx_bind(h.to_layout(Wn))
+        if dt is None:
+            dt = h.sx_compute_dt(case.cfl)
+        h.sx_set_flag_override(flags)
+        ms, kms = time_steps(h, dt, args.steps, args.warmup)
+        d = h.sx_diagnostics()
+        out[f"{frac:g}"] = {"ms_per_step": ms, "central_kernel_ms": kms,
+                            "weno_face_fraction": [float(f.mean()) for f in flags],
+                            "state_ok": d.status == sx.SX_OK}
+        del h, flags
+        torch.cuda.empty_cache()
+    base = out["0"]["ms_per_step"]
+    for v in out.values():
+        v["relative_to_no_weno"] = v["ms_per_step"] / base
     return out
 
 
@@ -397,6 +464,9 @@ def main():
         line["tgv32"] = bench_tgv(args)
         line["shock_bl"] = bench_shock_bl(args)
         line["fp32_flux"]["error_vs_fp64_after_100_steps"] = fp32_error(case, Wn, dt, 100)
+    if args.sweep:
+        line["order_sweep"] = bench_order_sweep(args, Wn, dt)
+        line["weno_activation_sweep"] = bench_activation_sweep(args)
     if not args.no_cpu_baseline:
         del h, W0
         torch.cuda.empty_cache()

@@ -60,8 +60,12 @@ def flux_scale(case, Wn):
     return np.array(F) / h
 
 
-@pytest.mark.parametrize("case", [inputs.tgv_case(32), inputs.channel_case(70, 36, 20)],
-                         ids=lambda c: c.name)
+@pytest.mark.parametrize("case", [inputs.tgv_case(32), inputs.channel_case(70, 36, 20),
+                                  inputs.tgv_case(24, central_order=2, visc_order=2),
+                                  inputs.tgv_case(24, central_order=4, visc_order=4),
+                                  inputs.tgv_case(24, central_order=8, visc_order=8),
+                                  inputs.channel_case(70, 36, 20, central_order=8, visc_order=8)],
+                         ids=lambda c: f"{c.name}-C{c.central_order}")
 def test_fp32_flux_rhs_error_is_fp32_rounding(case):
     Wn, got = _run_rhs(case, sx.SX_FP32_FLUX)
     ref = oracle_for(case).rhs(Wn.copy())
