@@ -22,9 +22,10 @@
 // Rprev.
 //
 // FP64 splits the work of a column between two waves (march_split): one
-// holds the convective terms, the column ring and the update, the other the
-// arrival plane, the mixed-derivative queues and the viscous terms, and
-// passes its part of the RHS through LDS. Each wave then needs under 256
+// holds the convective terms, the mixed x-y viscous terms and the update,
+// the other the arrival plane, the column ring, the mixed-derivative queues
+// and the remaining viscous terms, and passes its part of the RHS through
+// LDS. Each wave then needs under 256
 // registers, so every SIMD runs two waves whose instruction streams hide
 // each other's LDS and memory latencies (one wave of the unsplit FP64 march
 // needs ~390 registers and leaves the SIMD idle on every wait). FP32 halves
@@ -686,15 +687,26 @@ struct SmemSplit {
     R gyl[2][TY][HX];                                               // D_y u, D_y v of plane k
     __attribute__((aligned(16))) R zring[Q * NR * Layout<R>::ZREC]; // column records
     R xch[NV][NR];                                                  // viscous RHS of plane k
+    R vmu[NR];                                                      // viscosity of plane k (role 1 -> 0)
 };
 
 // Role-split march: the workgroup holds two threads per tile column. Role 0
-// (the first TX*TY threads) stages the output plane and the column ring,
-// evaluates the convective terms and applies the update; role 1 stages the
-// arrival plane, keeps the mixed-derivative queues and evaluates the
-// viscous terms, which it passes to role 0 through LDS. Each wave has one
-// role, so the two halves run as separate instruction streams that the
-// SIMDs interleave, and each holds half the per-column state.
+// (the first TX*TY threads) stages the output plane, evaluates the
+// convective terms and the mixed x-y viscous terms and applies the update;
+// role 1 stages the arrival plane and the column ring, keeps the
+// mixed-derivative queues, evaluates the viscosity before the plane barrier
+// (its own ring record is complete then) and the other viscous terms after
+// it, and passes them to role 0 through LDS. Each wave has one role, so the
+// two halves run as separate instruction streams that the SIMDs interleave,
+// and each holds half the per-column state. The work is divided so that
+// both roles reach the barriers at about the same time.
+//
+// Two barriers per plane: (1) after staging, (2) after the viscous hand-over.
+// No third one is needed before the next staging: every LDS buffer staged
+// for plane k+1 (output plane, arrival plane, the ring slot of plane k-S)
+// was last read before barrier 2 of plane k, the hand-over arrays are read
+// by role 0 before it reaches barrier 1 of plane k+1 and written again by
+// role 1 only after it, and the D_y rows are private to one wave.
 template <int S, int TX, int TY, typename R, bool UPD, bool PIMG>
 __device__ __forceinline__ void march_split(SmemSplit<S, TX, TY, R>& sm, const double* __restrict__ W,
                                             double* __restrict__ out, double* __restrict__ Rp,
@@ -715,6 +727,7 @@ __device__ __forceinline__ void march_split(SmemSplit<S, TX, TY, R>& sm, const d
     auto& gyl = sm.gyl;
     R* const zring = sm.zring;
     auto& xch = sm.xch;
+    auto& vmu = sm.vmu;
 
     constexpr bool f32 = std::is_same<R, float>::value;
     const double pref = f32 ? gas.pref : 0.0, href = f32 ? gas.href : 0.0;
@@ -770,11 +783,6 @@ __device__ __forceinline__ void march_split(SmemSplit<S, TX, TY, R>& sm, const d
 
     if (role == 0) {
         // ---- convective terms, column ring, update ----------------------
-        auto fetch_col = [&](double (&cq)[5], int k) {
-            const long long n = col + (long long)k * g.sz;
-#pragma unroll
-            for (int v = 0; v < 5; ++v) cq[v] = active ? W[n + v * g.sv] : (v == 0 ? 1.0 : 0.0);
-        };
         double wc[5], rp[5];
         auto fetch_centre = [&](int k) {
             const long long n = col + (long long)k * g.sz;
@@ -801,21 +809,12 @@ __device__ __forceinline__ void march_split(SmemSplit<S, TX, TY, R>& sm, const d
                 }
             }
         };
-        auto stage_column = [&](int slot, const double (&cq)[5]) {
-            double rho, u, v, w, T, p, H;
-            prims(cq, rho, u, v, w, T, p, H);
-            ring_write<R>(zring + L::ZREC * (slot * NR + tid), rho, u, v, w, T, p, H);
-        };
         PlaneFetch<NPT> fo;
-        double cq[5];
         for (int t = 0; t < 2 * S; ++t) {
-            fetch_col(cq, k0 - S + t);
-            stage_column(t, cq);
             __syncthreads();
             __syncthreads();
         }
         fetch(fo, k0, 5);
-        fetch_col(cq, k0 + S);
         fetch_centre(k0);
 
         double pend[NV] = {0, 0, 0, 0, 0};
@@ -850,11 +849,10 @@ __device__ __forceinline__ void march_split(SmemSplit<S, TX, TY, R>& sm, const d
             pend_n = -1;
         };
 
+        const R eyr = j < g.ny ? R(g.eta_y[j]) : R(0);
         int slot_k = S;
         for (int k = k0; k < k1; ++k) {
-            const int slot_new = slot_k + S >= Q ? slot_k + S - Q : slot_k + S;
             stage_output(fo);
-            stage_column(slot_new, cq);
             double wcur[5], rcur[5];
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
@@ -865,11 +863,47 @@ __device__ __forceinline__ void march_split(SmemSplit<S, TX, TY, R>& sm, const d
             __syncthreads();                                   // 1: planes staged
             if (k + 1 < k1) {
                 fetch(fo, k + 1, 5);
-                fetch_col(cq, k + 1 + S);
                 fetch_centre(k + 1);
             }
             sched_fence();
             R acc[NV] = {0, 0, 0, 0, 0};
+            // D_y u, D_y v over the x-extended columns of this thread's row;
+            // only this wave reads them (wavefront-scope ordering)
+            auto gy_at = [&](int hx) {
+                R su = 0, sv = 0;
+#pragma unroll
+                for (int l = 1; l <= S; ++l) {
+                    const int up = L::PREC * ((ty + S + l) * HX + hx), dn = L::PREC * ((ty + S - l) * HX + hx);
+                    su += R(Coef<S>::a[l]) * (so[up + L::OU] - so[dn + L::OU]);
+                    sv += R(Coef<S>::a[l]) * (so[up + L::OV] - so[dn + L::OV]);
+                }
+                gyl[0][ty][hx] = eyr * su;
+                gyl[1][ty][hx] = eyr * sv;
+            };
+            if (visc && j < g.ny) {
+                gy_at(tx + S);
+                if (tx < 2 * S) gy_at(tx < S ? tx : TX + tx);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (active && visc) {
+                // mixed x-y parts of mu/3 d_i(div u): d_x d_y v into x-momentum,
+                // d_x d_y u into y-momentum
+                R gyu[Q], gyv[Q];
+#pragma unroll
+                for (int t = 0; t < Q; ++t) {
+                    gyu[t] = gyl[0][ty][tx + t];
+                    gyv[t] = gyl[1][ty][tx + t];
+                }
+                const Node<R> Cc = getx(0);
+                const R m3 = vmu[tid] * R(1.0 / 3.0);
+                const R mxy = m3 * (dxi * d1<S>(gyv));
+                const R myx = m3 * (dxi * d1<S>(gyu));
+                acc[1] += mxy;
+                acc[2] += myx;
+                acc[4] += Cc.u * mxy + Cc.v * myx;
+            }
             if (active) {
                 R gd[4], dd[4];
                 auto getz = [&](int t) {
@@ -900,12 +934,10 @@ __device__ __forceinline__ void march_split(SmemSplit<S, TX, TY, R>& sm, const d
                 }
             }
             slot_k = slot_k + 1 == Q ? 0 : slot_k + 1;
-            __syncthreads();                                   // 3: planes consumed
         }
         flush();
     } else {
         // ---- arrival plane, mixed-derivative queues, viscous terms -------
-        const R eyr = j < g.ny ? R(g.eta_y[j]) : R(0);
         R m0[Q], m1[Q], m2[Q];   // D_x w, D_y w, D_x u + D_y v of this column
 #pragma unroll
         for (int t = 0; t < Q; ++t) m0[t] = m1[t] = m2[t] = R(0);
@@ -943,51 +975,60 @@ __device__ __forceinline__ void march_split(SmemSplit<S, TX, TY, R>& sm, const d
                 m2[t] = m2[t + 1];
             }
         };
+        // the column ring (z stencils of both roles) is staged here, from
+        // the arrival plane's own column point
+        auto fetch_col = [&](double (&cq)[5], int k) {
+            const long long n = col + (long long)k * g.sz;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) cq[v] = active ? W[n + v * g.sv] : (v == 0 ? 1.0 : 0.0);
+        };
+        auto stage_column = [&](int slot, const double (&cq)[5]) {
+            double rho, u, v, w, T, p, H;
+            prims(cq, rho, u, v, w, T, p, H);
+            ring_write<R>(zring + L::ZREC * (slot * NR + tid), rho, u, v, w, T, p, H);
+        };
         PlaneFetch<NPT> fa;
+        double cq[5];
         for (int t = 0; t < 2 * S; ++t) {
             fetch(fa, k0 - S + t, 4);
+            fetch_col(cq, k0 - S + t);
             stage_arrival(fa);
+            stage_column(t, cq);
             __syncthreads();
             arrive();
             shift();
             __syncthreads();
         }
         fetch(fa, k0 + S, 4);
+        fetch_col(cq, k0 + S);
 
         int slot_k = S;
         for (int k = k0; k < k1; ++k) {
+            const int slot_new = slot_k + S >= Q ? slot_k + S - Q : slot_k + S;
             stage_arrival(fa);
-            __syncthreads();                                   // 1: planes staged
-            arrive();
-            if (k + 1 < k1) fetch(fa, k + 1 + S, 4);
-            sched_fence();
-            // D_y u, D_y v over the x-extended columns of this thread's row;
-            // only this wave reads them (wavefront-scope ordering)
-            auto gy_at = [&](int hx) {
-                R su = 0, sv = 0;
-#pragma unroll
-                for (int l = 1; l <= S; ++l) {
-                    const int up = L::PREC * ((ty + S + l) * HX + hx), dn = L::PREC * ((ty + S - l) * HX + hx);
-                    su += R(Coef<S>::a[l]) * (so[up + L::OU] - so[dn + L::OU]);
-                    sv += R(Coef<S>::a[l]) * (so[up + L::OV] - so[dn + L::OV]);
-                }
-                gyl[0][ty][hx] = eyr * su;
-                gyl[1][ty][hx] = eyr * sv;
-            };
-            if (visc && j < g.ny) {
-                gy_at(tx + S);
-                if (tx < 2 * S) gy_at(tx < S ? tx : TX + tx);
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            R acc[NV] = {0, 0, 0, 0, 0};
+            stage_column(slot_new, cq);
+            // viscosity of plane k from this thread's own ring record
+            R uc = 0, vc = 0, wc_ = 0, mu = 0, kcd = 0, smt = 0;
             if (active && visc) {
                 const Node<R> Cz = znode(slot_k);
-                const R uc = Cz.u, vc = Cz.v, wc_ = Cz.w, Tc = Cz.T;
-                const R mu = visc_pow<R>(Tc, gas) * R(gas.ire);
-                const R kcd = mu * R(gas.cp * gas.ipr);
-                const R smt = R(gas.s) * rcpr<R>(Tc);
+                uc = Cz.u;
+                vc = Cz.v;
+                wc_ = Cz.w;
+                const R Tc = Cz.T;
+                mu = visc_pow<R>(Tc, gas) * R(gas.ire);
+                kcd = mu * R(gas.cp * gas.ipr);
+                smt = R(gas.s) * rcpr<R>(Tc);
+                vmu[tid] = mu;
+            }
+            __syncthreads();                                   // 1: planes staged
+            arrive();
+            if (k + 1 < k1) {
+                fetch(fa, k + 1 + S, 4);
+                fetch_col(cq, k + 1 + S);
+            }
+            sched_fence();
+            R acc[NV] = {0, 0, 0, 0, 0};
+            if (active && visc) {
                 R gx[4], gy[4], gz[4], dd[4];
                 auto getz = [&](int t) {
                     int sl = slot_k + t;
@@ -1000,16 +1041,11 @@ __device__ __forceinline__ void march_split(SmemSplit<S, TX, TY, R>& sm, const d
                 visc_linear<1>(dd, mu, kcd, uc, vc, wc_, acc);
                 stencil_dir<S, 2, false, true>(getz, dzi, dzi * dzi, R(0), acc, gz, dd);
                 visc_linear<2>(dd, mu, kcd, uc, vc, wc_, acc);
-                // mixed parts of mu/3 d_i(div u): d_x d_y, d_x d_z, d_y d_z
-                R gyu[Q], gyv[Q];
-#pragma unroll
-                for (int t = 0; t < Q; ++t) {
-                    gyu[t] = gyl[0][ty][tx + t];
-                    gyv[t] = gyl[1][ty][tx + t];
-                }
+                // mixed z parts of mu/3 d_i(div u): d_z d_x w, d_z d_y w,
+                // d_z (d_x u + d_y v) (the x-y parts are the convective role's)
                 const R m3 = mu * R(1.0 / 3.0);
-                const R mx = m3 * (dxi * d1<S>(gyv) + dzi * d1<S>(m0));
-                const R my = m3 * (dxi * d1<S>(gyu) + dzi * d1<S>(m1));
+                const R mx = m3 * (dzi * d1<S>(m0));
+                const R my = m3 * (dzi * d1<S>(m1));
                 const R mz = m3 * (dzi * d1<S>(m2));
                 acc[1] += mx;
                 acc[2] += my;
@@ -1039,7 +1075,6 @@ __device__ __forceinline__ void march_split(SmemSplit<S, TX, TY, R>& sm, const d
             __syncthreads();                                   // 2: viscous part ready
             shift();
             slot_k = slot_k + 1 == Q ? 0 : slot_k + 1;
-            __syncthreads();                                   // 3: planes consumed
         }
     }
 }
