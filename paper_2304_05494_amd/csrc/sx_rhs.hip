@@ -1149,19 +1149,22 @@ __global__ void k_set_value(double* p, double v)
     if (threadIdx.x == 0) p[0] = v;
 }
 
-// Tile shapes: FP64 keeps one wave per SIMD (registers), so 256 threads per
-// workgroup: 32x8 up to sixth order (the smaller halo ratio, 38x14 staged
-// nodes per 256 outputs instead of 70x10, outweighs the shorter rows),
-// 64x2 for the eighth-order stencil (LDS); FP32 halves registers and LDS,
-// so 512-thread 64x8 tiles with two waves per SIMD (64x4 at eighth order).
+// Tile shapes (columns along x by rows along y): FP64 runs the two-role
+// split, 32x8 columns (512 threads) up to sixth order -- the smaller halo
+// ratio (38x14 staged nodes per 256 outputs instead of 70x10) outweighs the
+// shorter rows. FP32 up to sixth order runs the unsplit march on 64x8 tiles,
+// two waves per SIMD. At eighth order the nine-plane column ring and the
+// wider halo leave LDS for 32x4 split tiles only (256 threads), in both
+// precision forms: FP32 then fits two workgroups per CU (two waves per
+// SIMD), FP64 one.
 template <typename R, int S>
 struct Tile {
     static constexpr bool F32 = std::is_same<R, float>::value;
-    static constexpr bool SPLIT = !F32;
-    static constexpr int TX = (!F32 && S <= 3) ? 32 : 64;
-    static constexpr int TY = F32 ? (S <= 3 ? 8 : 4) : (S <= 3 ? 8 : 2);
+    static constexpr bool SPLIT = !F32 || S > 3;
+    static constexpr int TX = SPLIT ? 32 : 64;
+    static constexpr int TY = S <= 3 ? 8 : 4;
     static constexpr int NTH = TX * TY * (SPLIT ? 2 : 1);
-    static constexpr int WPE = F32 ? 2 : (SPLIT ? 2 : 1);
+    static constexpr int WPE = 2;
 };
 
 template <int S, typename R>

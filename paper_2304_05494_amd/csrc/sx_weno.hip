@@ -50,7 +50,7 @@ __device__ __forceinline__ int map_ghost(int i, int n, int bc_lo, int bc_hi)
 // TYT column tile and marches a chunk of TZT planes; velocities of three
 // planes (tile + one halo node, read from the ghosted state) sit in an LDS
 // ring, so each node's velocity is formed once.
-constexpr int TXT = 64, TYT = 4, TZT = 16;
+constexpr int TXT = 64, TYT = 8, TZT = 16;
 __global__ void __launch_bounds__(TXT * TYT) k_theta(KGrid g, double eps, const double* __restrict__ W,
                                                      double* __restrict__ theta)
 {
@@ -113,7 +113,7 @@ __global__ void __launch_bounds__(TXT * TYT) k_theta(KGrid g, double eps, const 
 // marches a chunk of FZ planes: theta of the plane with an r-wide x/y halo
 // sits in LDS (x and y maxima), each thread keeps its column's last 2r
 // theta values in registers (z maxima).
-constexpr int FX = 64, FY = 4, RMAX = 4, FZ = 16;   // tile and z-chunk of k_flags
+constexpr int FX = 64, FY = 8, RMAX = 4, FZ = 16;   // tile and z-chunk of k_flags
 __global__ void __launch_bounds__(FX * FY) k_flags(KGrid g, int r, double thr,
                                                    const double* __restrict__ theta, WenoBufs b)
 {
