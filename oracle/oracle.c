@@ -15,8 +15,8 @@
  *  - viscous terms expanded in Laplacian form, central FD order 2..8;
  *  - third-order low-storage Runge-Kutta in time.
  * The paper states these only in words; every concrete formula below is the
- * published method it names (or the reading recorded in the design doc), each
- * marked at its function.
+ * published method it names or, where the paper is silent, the reading
+ * stated at the function.
  */
 #include "oracle.h"
 
