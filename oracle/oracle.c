@@ -256,10 +256,10 @@ void orc_primitives(const orc_params* p, const double* W, double* Q)
 }
 
 /* ------------------------------------------------------------------ */
-/* Ghost fill (paper is silent on boundary formulas; readings in the    */
-/* design notes). Directions are filled in the order x, y, z; each      */
-/* covers the full ghosted extent of the directions filled before it,   */
-/* so edge and corner ghosts are consistent.                            */
+/* Ghost fill (the paper states no boundary formulas; the readings     */
+/* used are listed below). Directions are filled in the order x, y, z; */
+/* each covers the full ghosted extent of the directions filled before */
+/* it, so edge and corner ghosts are consistent.                        */
 /*  periodic : ghost i = -1-l <- nx-1-l,  i = nx+l <- l                 */
 /*  wall     : isothermal no-slip by reflection about the wall face:    */
 /*             u,v,w odd, p even, T_g = 2 T_w - T_m, rho from the EOS   */
