@@ -134,7 +134,9 @@ typedef struct sx_handle sx_handle;
  * the node coordinates, central order) and uploads them. Allocates the
  * library-owned device buffers: metrics and reduction scratch, plus the
  * hybrid scheme's work arrays when the sensor is on (see sx_scheme). On
- * error *out is NULL. */
+ * error *out is NULL. SX_EINVAL also when one variable of the ghosted
+ * state, or of the interior RK register, would exceed 4 GiB (the kernels
+ * address within a variable by 32-bit byte offsets). */
 int sx_init(const sx_grid* grid, const sx_gas* gas, const sx_scheme* scheme,
             sx_handle** out);
 

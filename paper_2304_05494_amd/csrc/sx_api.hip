@@ -119,6 +119,12 @@ int sx_validate(const sx_grid& g, const sx_gas& gas, const sx_scheme& s, int* ng
             if (g.bc[2 * d + sd] < SX_BC_PERIODIC || g.bc[2 * d + sd] > SX_BC_FROZEN) return SX_EINVAL;
         if ((g.bc[2 * d] == SX_BC_PERIODIC) != (g.bc[2 * d + 1] == SX_BC_PERIODIC)) return SX_EINVAL;
     }
+    // the kernels address one variable of the ghosted state, and of the RK
+    // register, with 32-bit byte offsets: each must stay below 4 GiB
+    const long long px = ((16LL + g.nx + ng + 15) / 16) * 16;
+    const long long var_bytes = 8 * px * (g.ny + 2LL * ng) * (g.nz + 2LL * ng);
+    const long long int_bytes = 8LL * g.nx * g.ny * g.nz;
+    if (var_bytes >= (1LL << 32) || int_bytes >= (1LL << 32)) return SX_EINVAL;
     *ng_out = ng;
     return SX_OK;
 }

@@ -331,6 +331,18 @@ struct Smem {
 // March one column tile (i0, j0) of one block over planes [k0, k1).
 // PIMG: every direction is periodic and the new state is also written into
 // its periodic ghost images, so the next substep needs no ghost fill.
+// Load / store at a byte offset from a base pointer.
+template <typename T>
+__device__ __forceinline__ T ldo(const T* base, unsigned bo)
+{
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + bo);
+}
+template <typename T>
+__device__ __forceinline__ void sto(T* base, unsigned bo, T v)
+{
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + bo) = v;
+}
+
 template <int S, int TX, int TY, typename R, bool UPD, bool PIMG>
 __device__ __forceinline__ void march(Smem<S, TX, TY, R>& sm, const double* __restrict__ W,
                                       double* __restrict__ out, double* __restrict__ Rp,
@@ -369,44 +381,53 @@ __device__ __forceinline__ void march(Smem<S, TX, TY, R>& sm, const double* __re
 #pragma unroll
     for (int t = 0; t < Q; ++t) m0[t] = m1[t] = m2[t] = R(0);
 
-    auto halo_index = [&](int q, int k) -> long long {
+    // Global accesses: per-variable base pointer plus a 32-bit byte offset
+    // (in-plane part per thread, plane part uniform); see march_split.
+    const unsigned colbo = (unsigned)(col * 8);
+    const unsigned jibo = (unsigned)(((long long)j * g.nx + i) * 8);
+    auto kbo = [&](int k) { return (unsigned)((long long)k * g.sz * 8); };
+    auto kbr = [&](int k) { return (unsigned)((long long)k * g.ny * g.nx * 8); };
+    unsigned hbo[NPT];
+    bool hok[NPT];
+#pragma unroll
+    for (int a = 0; a < NPT; ++a) {
+        const int q = tid + a * NT;
         const int hx = q % HX, hy = q / HX;
         const int gi = i0 - S + hx, gj = j0 - S + hy;
-        if (q < HP && gi >= -g.ng && gi < g.nx + g.ng && gj >= -g.ng && gj < g.ny + g.ng)
-            return g.base + (long long)k * g.sz + (long long)gj * g.sy + gi;
-        return -1;
-    };
+        hok[a] = q < HP && gi >= -g.ng && gi < g.nx + g.ng && gj >= -g.ng && gj < g.ny + g.ng;
+        hbo[a] = hok[a] ? (unsigned)((g.base + (long long)gj * g.sy + gi) * 8) : 0u;
+    }
     auto fetch = [&](PlaneFetch<NPT>& f, int k, int nvar) {
+        const unsigned kb = kbo(k);
 #pragma unroll
         for (int a = 0; a < NPT; ++a) {
-            const long long n = halo_index(tid + a * NT, k);
             f.q[a][0] = 1.0;
             f.q[a][1] = f.q[a][2] = f.q[a][3] = 0.0;
             f.q[a][4] = 1.0;
-            if (n >= 0) {
+            if (hok[a]) {
+                const unsigned bo = hbo[a] + kb;
 #pragma unroll
                 for (int v = 0; v < 5; ++v)
-                    if (v < nvar) f.q[a][v] = W[n + v * g.sv];
+                    if (v < nvar) f.q[a][v] = ldo(W + v * g.sv, bo);
             }
         }
     };
     auto fetch_col = [&](double (&cq)[5], int k) {
-        const long long n = col + (long long)k * g.sz;
+        const unsigned bn = colbo + kbo(k);
 #pragma unroll
-        for (int v = 0; v < 5; ++v) cq[v] = active ? W[n + v * g.sv] : (v == 0 ? 1.0 : 0.0);
+        for (int v = 0; v < 5; ++v) cq[v] = active ? ldo(W + v * g.sv, bn) : (v == 0 ? 1.0 : 0.0);
     };
     double wc[5], rp[5];   // centre state and RK register of the next output node
     auto fetch_centre = [&](int k) {
-        const long long n = col + (long long)k * g.sz;
-        const long long m = ((long long)k * g.ny + j) * g.nx + i;
+        const unsigned bn = colbo + kbo(k), bm = jibo + kbr(k);
 #pragma unroll
         for (int v = 0; v < 5; ++v) wc[v] = rp[v] = 0.0;
         if (UPD && active) {
 #pragma unroll
-            for (int v = 0; v < 5; ++v) wc[v] = W[n + v * g.sv];
+            for (int v = 0; v < 5; ++v) wc[v] = ldo(W + v * g.sv, bn);
             if (sc.read_prev) {
 #pragma unroll
-                for (int v = 0; v < 5; ++v) rp[v] = Rp[m + v * g.nint];
+                for (int v = 0; v < 5; ++v) rp[v] = ldo(Rp + v * g.nint, bm);
             }
         }
     };
@@ -500,35 +521,38 @@ __device__ __forceinline__ void march(Smem<S, TX, TY, R>& sm, const double* __re
     // results of the previous output plane, stored one iteration late
     double pend[NV] = {0, 0, 0, 0, 0};
     double pend_w[NV] = {0, 0, 0, 0, 0};
-    long long pend_n = -1, pend_m = -1;
+    int pend_k = -1;   // plane of the pending stores, -1: none
     auto flush = [&]() {
-        if (pend_n < 0) return;
+        if (pend_k < 0) return;
         if (UPD) {
+            const unsigned bn = colbo + kbo(pend_k);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) out[v * g.sv + pend_n] = pend_w[v];
+            for (int v = 0; v < NV; ++v) sto(out + v * g.sv, bn, pend_w[v]);
             if constexpr (PIMG) {
                 // periodic images of node (i, j, pend_k) inside the ghost layers
-                const int kk = (int)((pend_n - col) / g.sz);
+                const int kk = pend_k;
                 const int ox = i < g.ng ? g.nx : (i >= g.nx - g.ng ? -g.nx : 0);
                 const int oy = j < g.ng ? g.ny : (j >= g.ny - g.ng ? -g.ny : 0);
                 const int oz = kk < g.ng ? g.nz : (kk >= g.nz - g.ng ? -g.nz : 0);
                 for (int c3 = 1; c3 < 8; ++c3) {
                     const int dx = (c3 & 1) ? ox : 0, dy = (c3 & 2) ? oy : 0, dz = (c3 & 4) ? oz : 0;
                     if (((c3 & 1) && !ox) || ((c3 & 2) && !oy) || ((c3 & 4) && !oz)) continue;
-                    const long long e = pend_n + dx + (long long)dy * g.sy + (long long)dz * g.sz;
+                    const unsigned be = bn + (unsigned)((dx + (long long)dy * g.sy + (long long)dz * g.sz) * 8);
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) out[v * g.sv + e] = pend_w[v];
+                    for (int v = 0; v < NV; ++v) sto(out + v * g.sv, be, pend_w[v]);
                 }
             }
             if (sc.write_prev) {
+                const unsigned bm = jibo + kbr(pend_k);
 #pragma unroll
-                for (int v = 0; v < NV; ++v) Rp[v * g.nint + pend_m] = pend[v];
+                for (int v = 0; v < NV; ++v) sto(Rp + v * g.nint, bm, pend[v]);
             }
         } else {
+            const unsigned bm = jibo + kbr(pend_k);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) out[v * g.nint + pend_m] = pend[v];
+            for (int v = 0; v < NV; ++v) sto(out + v * g.nint, bm, pend[v]);
         }
-        pend_n = -1;
+        pend_k = -1;
     };
 
     int slot_k = S;   // ring slot of the output plane k (plane k0-S sits in slot 0)
@@ -653,8 +677,7 @@ __device__ __forceinline__ void march(Smem<S, TX, TY, R>& sm, const double* __re
                 acc[3] += N2;
                 acc[4] += uc * N0 + vc * N1 + wc_ * N2 + diss + (smt * kcd) * (Tx * Tx + Ty * Ty + Tz * Tz);
             }
-            pend_m = ((long long)k * g.ny + j) * g.nx + i;
-            pend_n = col + (long long)k * g.sz;
+            pend_k = k;
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 double r = double(acc[v]);
@@ -744,24 +767,37 @@ __device__ __forceinline__ void march_split(SmemSplit<S, TX, TY, R>& sm, const d
     const long long col = g.base + (long long)j * g.sy + i;
     const bool visc = mask & SX_VISC;
 
-    auto halo_index = [&](int q, int k) -> long long {
+    // Global accesses take a per-variable base pointer (uniform, scalar
+    // registers) plus a 32-bit byte offset: the in-plane part is fixed per
+    // thread, the plane part k*sz is uniform, so each load or store costs
+    // one vector add. The host keeps every array of one variable below
+    // 4 GiB.
+    const unsigned colbo = (unsigned)(col * 8);
+    const unsigned jibo = (unsigned)(((long long)j * g.nx + i) * 8);
+    auto kbo = [&](int k) { return (unsigned)((long long)k * g.sz * 8); };
+    auto kbr = [&](int k) { return (unsigned)((long long)k * g.ny * g.nx * 8); };
+    unsigned hbo[NPT];
+    bool hok[NPT];
+#pragma unroll
+    for (int a = 0; a < NPT; ++a) {
+        const int q = tid + a * NR;
         const int hx = q % HX, hy = q / HX;
         const int gi = i0 - S + hx, gj = j0 - S + hy;
-        if (q < HP && gi >= -g.ng && gi < g.nx + g.ng && gj >= -g.ng && gj < g.ny + g.ng)
-            return g.base + (long long)k * g.sz + (long long)gj * g.sy + gi;
-        return -1;
-    };
+        hok[a] = q < HP && gi >= -g.ng && gi < g.nx + g.ng && gj >= -g.ng && gj < g.ny + g.ng;
+        hbo[a] = hok[a] ? (unsigned)((g.base + (long long)gj * g.sy + gi) * 8) : 0u;
+    }
     auto fetch = [&](PlaneFetch<NPT>& f, int k, int nvar) {
+        const unsigned kb = kbo(k);
 #pragma unroll
         for (int a = 0; a < NPT; ++a) {
-            const long long n = halo_index(tid + a * NR, k);
             f.q[a][0] = 1.0;
             f.q[a][1] = f.q[a][2] = f.q[a][3] = 0.0;
             f.q[a][4] = 1.0;
-            if (n >= 0) {
+            if (hok[a]) {
+                const unsigned bo = hbo[a] + kb;
 #pragma unroll
                 for (int v = 0; v < 5; ++v)
-                    if (v < nvar) f.q[a][v] = W[n + v * g.sv];
+                    if (v < nvar) f.q[a][v] = ldo(W + v * g.sv, bo);
             }
         }
     };
@@ -785,16 +821,15 @@ __device__ __forceinline__ void march_split(SmemSplit<S, TX, TY, R>& sm, const d
         // ---- convective terms, column ring, update ----------------------
         double wc[5], rp[5];
         auto fetch_centre = [&](int k) {
-            const long long n = col + (long long)k * g.sz;
-            const long long m = ((long long)k * g.ny + j) * g.nx + i;
+            const unsigned bn = colbo + kbo(k), bm = jibo + kbr(k);
 #pragma unroll
             for (int v = 0; v < 5; ++v) wc[v] = rp[v] = 0.0;
             if (UPD && active) {
 #pragma unroll
-                for (int v = 0; v < 5; ++v) wc[v] = W[n + v * g.sv];
+                for (int v = 0; v < 5; ++v) wc[v] = ldo(W + v * g.sv, bn);
                 if (sc.read_prev) {
 #pragma unroll
-                    for (int v = 0; v < 5; ++v) rp[v] = Rp[m + v * g.nint];
+                    for (int v = 0; v < 5; ++v) rp[v] = ldo(Rp + v * g.nint, bm);
                 }
             }
         };
@@ -819,34 +854,37 @@ __device__ __forceinline__ void march_split(SmemSplit<S, TX, TY, R>& sm, const d
 
         double pend[NV] = {0, 0, 0, 0, 0};
         double pend_w[NV] = {0, 0, 0, 0, 0};
-        long long pend_n = -1, pend_m = -1;
+        int pend_k = -1;   // plane of the pending stores, -1: none
         auto flush = [&]() {
-            if (pend_n < 0) return;
+            if (pend_k < 0) return;
             if (UPD) {
+                const unsigned bn = colbo + kbo(pend_k);
 #pragma unroll
-                for (int v = 0; v < NV; ++v) out[v * g.sv + pend_n] = pend_w[v];
+                for (int v = 0; v < NV; ++v) sto(out + v * g.sv, bn, pend_w[v]);
                 if constexpr (PIMG) {
-                    const int kk = (int)((pend_n - col) / g.sz);
+                    const int kk = pend_k;
                     const int ox = i < g.ng ? g.nx : (i >= g.nx - g.ng ? -g.nx : 0);
                     const int oy = j < g.ng ? g.ny : (j >= g.ny - g.ng ? -g.ny : 0);
                     const int oz = kk < g.ng ? g.nz : (kk >= g.nz - g.ng ? -g.nz : 0);
                     for (int c3 = 1; c3 < 8; ++c3) {
                         const int dx = (c3 & 1) ? ox : 0, dy = (c3 & 2) ? oy : 0, dz = (c3 & 4) ? oz : 0;
                         if (((c3 & 1) && !ox) || ((c3 & 2) && !oy) || ((c3 & 4) && !oz)) continue;
-                        const long long e = pend_n + dx + (long long)dy * g.sy + (long long)dz * g.sz;
+                        const unsigned be = bn + (unsigned)((dx + (long long)dy * g.sy + (long long)dz * g.sz) * 8);
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) out[v * g.sv + e] = pend_w[v];
+                        for (int v = 0; v < NV; ++v) sto(out + v * g.sv, be, pend_w[v]);
                     }
                 }
                 if (sc.write_prev) {
+                    const unsigned bm = jibo + kbr(pend_k);
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) Rp[v * g.nint + pend_m] = pend[v];
+                    for (int v = 0; v < NV; ++v) sto(Rp + v * g.nint, bm, pend[v]);
                 }
             } else {
+                const unsigned bm = jibo + kbr(pend_k);
 #pragma unroll
-                for (int v = 0; v < NV; ++v) out[v * g.nint + pend_m] = pend[v];
+                for (int v = 0; v < NV; ++v) sto(out + v * g.nint, bm, pend[v]);
             }
-            pend_n = -1;
+            pend_k = -1;
         };
 
         const R eyr = j < g.ny ? R(g.eta_y[j]) : R(0);
@@ -919,8 +957,7 @@ __device__ __forceinline__ void march_split(SmemSplit<S, TX, TY, R>& sm, const d
             if (active) {
                 // enthalpy shift correction of the convective energy flux (FP64)
                 const double accE_shift = href * double(acc[0]);
-                pend_m = ((long long)k * g.ny + j) * g.nx + i;
-                pend_n = col + (long long)k * g.sz;
+                pend_k = k;
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
                     double r = double(acc[v] + xch[v][tid]);
@@ -978,9 +1015,9 @@ __device__ __forceinline__ void march_split(SmemSplit<S, TX, TY, R>& sm, const d
         // the column ring (z stencils of both roles) is staged here, from
         // the arrival plane's own column point
         auto fetch_col = [&](double (&cq)[5], int k) {
-            const long long n = col + (long long)k * g.sz;
+            const unsigned bn = colbo + kbo(k);
 #pragma unroll
-            for (int v = 0; v < 5; ++v) cq[v] = active ? W[n + v * g.sv] : (v == 0 ? 1.0 : 0.0);
+            for (int v = 0; v < 5; ++v) cq[v] = active ? ldo(W + v * g.sv, bn) : (v == 0 ? 1.0 : 0.0);
         };
         auto stage_column = [&](int slot, const double (&cq)[5]) {
             double rho, u, v, w, T, p, H;

@@ -74,6 +74,7 @@ def _init(case, **patch):
     ({"gamma": 1.0}, sx.SX_EINVAL),
     ({"lx": 0.0}, sx.SX_EINVAL),
     ({"ymap": 9}, sx.SX_EINVAL),
+    ({"nx": 1024, "ny": 1024, "nz": 1024}, sx.SX_EINVAL),   # over 4 GiB per variable
 ])
 def test_invalid_descriptions_rejected_without_device(patch, code):
     rc, h = _init(inputs.tgv_case(16), **patch)
