@@ -1186,6 +1186,20 @@ __global__ void k_set_value(double* p, double v)
     if (threadIdx.x == 0) p[0] = v;
 }
 
+// Compute units of the current device (queried once).
+static int device_cus()
+{
+    static int n = 0;
+    if (!n) {
+        int dev = 0, c = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
+            c = 256;
+        n = c;
+    }
+    return n;
+}
+
 // Tile shapes (columns along x by rows along y): FP64 runs the two-role
 // split, 32x8 columns (512 threads) up to sixth order -- the smaller halo
 // ratio (38x14 staged nodes per 256 outputs instead of 70x10) outweighs the
@@ -1212,12 +1226,28 @@ static hipError_t launch_rhs_SR(const KGrid& g, const KGas& gas, const double* W
     constexpr int TX = Tile<R, S>::TX, TY = Tile<R, S>::TY, WPE = Tile<R, S>::WPE;
     constexpr bool SP = Tile<R, S>::SPLIT;
     constexpr int NTH = Tile<R, S>::NTH;
-    // One march over the whole z extent per column tile, unless the block
-    // has too few tiles to fill the device: then z is cut into chunks (each
-    // chunk pays a 2S-plane prologue) until there are about 512 workgroups,
-    // keeping chunks of at least 8 planes.
+    // z is cut into nch chunks, each marched by its own workgroup after a
+    // 2S-plane prologue. The count minimises the modelled march length:
+    // rounds of workgroups over the CUs (one resident workgroup per CU)
+    // times the planes each one steps through. Blocks with at least one
+    // tile per CU march whole columns; small blocks, latency-bound, get
+    // short chunks (a 32^3 block: one plane per workgroup).
     const int ntiles = ((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY);
-    const int nch = max(1, min(512 / ntiles, g.nz / 8));
+    const int cus = device_cus();
+    int nch = 1;
+    if (ntiles < cus) {
+        long long best = -1;
+        const int cmax = min(g.nz, 2 * cus);
+        for (int c = 1; c <= cmax; ++c) {
+            const int kcc = (g.nz + c - 1) / c;
+            const long long rounds = ((long long)ntiles * ((g.nz + kcc - 1) / kcc) + cus - 1) / cus;
+            const long long t = rounds * (kcc + 2 * S);
+            if (best < 0 || t < best) {
+                best = t;
+                nch = c;
+            }
+        }
+    }
     const int kc = (g.nz + nch - 1) / nch;
     dim3 grid((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY, (g.nz + kc - 1) / kc);
     if (step && pimg) {
