@@ -508,6 +508,10 @@ __global__ void __launch_bounds__(WB) k_weno_node(KGrid g, unsigned mask, WenoBu
     }
 }
 
+// Grid of the grid-stride face and node passes: four 256-thread workgroups
+// per CU (measured on the shock/boundary-layer block: the node pass 14 %
+// faster than with eight, the face passes unchanged, one or two per CU
+// slower).
 int persistent_blocks()
 {
     static int nb = 0;
@@ -516,7 +520,7 @@ int persistent_blocks()
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             cus = 256;
-        nb = 8 * cus;
+        nb = 4 * cus;
     }
     return nb;
 }
