@@ -194,6 +194,18 @@ class Oracle:
         lib().orc_face_flags(ctypes.byref(self._c), _dp(th), _up(fx), _up(fy), _up(fz))
         return fx, fy, fz
 
+    def face_flags_from_theta(self, theta: np.ndarray):
+        """Face flags of a given ghosted sensor field (the hybrid switch
+        alone, without the sensor evaluation)."""
+        p = self.params
+        theta = np.ascontiguousarray(theta, dtype=np.float64)
+        assert theta.shape == self.ghosted_shape
+        fx = np.zeros((p.nz, p.ny, p.nx + 1), np.uint8)
+        fy = np.zeros((p.nz, p.ny + 1, p.nx), np.uint8)
+        fz = np.zeros((p.nz + 1, p.ny, p.nx), np.uint8)
+        lib().orc_face_flags(ctypes.byref(self._c), _dp(theta), _up(fx), _up(fy), _up(fz))
+        return fx, fy, fz
+
     def rhs(self, W: np.ndarray, mask: int = ALL, flags=None) -> np.ndarray:
         R = np.zeros((5,) + self.interior_shape)
         fx = fy = fz = None
