@@ -118,6 +118,7 @@ def lib():
         L.orc_fd_coeffs.argtypes = [ctypes.c_int, dp, dp]
         L.orc_weno_left.argtypes = [ctypes.c_int, ctypes.c_double, dp]
         L.orc_weno_left.restype = ctypes.c_double
+        L.orc_weno_smoothness.argtypes = [ctypes.c_int, dp, dp]
         L.orc_char_basis.argtypes = [ctypes.c_double] * 5 + [dp, dp]
         L.orc_face_flux_1d.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                        ctypes.c_double, ctypes.c_int, dp, dp]
@@ -244,6 +245,13 @@ def fd_coeffs(order: int):
 def weno_left(order: int, eps: float, v) -> float:
     v = np.ascontiguousarray(v, dtype=np.float64)
     return lib().orc_weno_left(order, eps, _dp(v))
+
+
+def weno_smoothness(order: int, v) -> np.ndarray:
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    beta = np.zeros(4)
+    lib().orc_weno_smoothness(order, _dp(v), _dp(beta))
+    return beta[:(order + 1) // 2]
 
 
 def char_basis(gamma, un, ut1, ut2, H):

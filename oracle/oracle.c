@@ -82,7 +82,7 @@ int orc_validate(const orc_params* p)
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return 1;
     if (p->central_order < 2 || p->central_order > 8 || p->central_order % 2) return 2;
     if (p->visc_order < 2 || p->visc_order > 8 || p->visc_order % 2) return 3;
-    if (p->weno_order != 1 && p->weno_order != 3 && p->weno_order != 5) return 4;
+    if (p->weno_order != 1 && p->weno_order != 3 && p->weno_order != 5 && p->weno_order != 7) return 4;
     for (d = 0; d < 3; ++d) {
         int n = d == 0 ? p->nx : (d == 1 ? p->ny : p->nz);
         if ((p->bc[2 * d] == ORC_BC_PERIODIC) != (p->bc[2 * d + 1] == ORC_BC_PERIODIC)) return 5;
@@ -473,39 +473,83 @@ static void central_flux_line(int L, const double* a, int d,
 /*    basis (rho, rho u_n, rho u_t1, rho u_t2, rho E);                   */
 /*  - local Lax-Friedrichs splitting per characteristic field, lambda_k */
 /*    = max over the stencil nodes of |eigenvalue k|;                    */
-/*  - Jiang-Shu WENO of order 2r-1 (r = 1, 2, 3).                       */
+/*  - Jiang-Shu WENO of order 2r-1 (r = 1, 2, 3), and for the paper's   */
+/*    "up to seventh order" the Balsara-Shu scheme (r = 4).             */
 /* ------------------------------------------------------------------ */
+/* Smoothness indicators of the r candidate stencils (Jiang-Shu: the sum
+ * over derivative orders l = 1..r-1 of the integral over the reconstruction
+ * cell of h^(2l-1) (d^l p_k / dx^l)^2, p_k the stencil's reconstruction
+ * polynomial). v holds v_{i-r+1} .. v_{i+r-1}. Order 7 is the Balsara-Shu
+ * scheme: quadratic forms with denominator 240. */
+static void weno_smoothness(int order, const double* v, double* beta)
+{
+    double t;
+    if (order == 3) {
+        double vm = v[0], v0 = v[1], vp = v[2];
+        beta[0] = (v0 - vm) * (v0 - vm);
+        beta[1] = (vp - v0) * (vp - v0);
+    } else if (order == 5) {
+        double vmm = v[0], vm = v[1], v0 = v[2], vp = v[3], vpp = v[4];
+        t = vmm - 2.0 * vm + v0; beta[0] = 13.0 / 12.0 * t * t;
+        t = vmm - 4.0 * vm + 3.0 * v0; beta[0] += 0.25 * t * t;
+        t = vm - 2.0 * v0 + vp; beta[1] = 13.0 / 12.0 * t * t;
+        t = vm - vp; beta[1] += 0.25 * t * t;
+        t = v0 - 2.0 * vp + vpp; beta[2] = 13.0 / 12.0 * t * t;
+        t = 3.0 * v0 - 4.0 * vp + vpp; beta[2] += 0.25 * t * t;
+    } else if (order == 7) {
+        double a = v[0], b = v[1], c = v[2], d = v[3], e = v[4], f = v[5], g = v[6];
+        beta[0] = (a * (547.0 * a - 3882.0 * b + 4642.0 * c - 1854.0 * d)
+                   + b * (7043.0 * b - 17246.0 * c + 7042.0 * d)
+                   + c * (11003.0 * c - 9402.0 * d) + 2107.0 * d * d) / 240.0;
+        beta[1] = (b * (267.0 * b - 1642.0 * c + 1602.0 * d - 494.0 * e)
+                   + c * (2843.0 * c - 5966.0 * d + 1922.0 * e)
+                   + d * (3443.0 * d - 2522.0 * e) + 547.0 * e * e) / 240.0;
+        beta[2] = (c * (547.0 * c - 2522.0 * d + 1922.0 * e - 494.0 * f)
+                   + d * (3443.0 * d - 5966.0 * e + 1602.0 * f)
+                   + e * (2843.0 * e - 1642.0 * f) + 267.0 * f * f) / 240.0;
+        beta[3] = (d * (2107.0 * d - 9402.0 * e + 7042.0 * f - 1854.0 * g)
+                   + e * (11003.0 * e - 17246.0 * f + 4642.0 * g)
+                   + f * (7043.0 * f - 3882.0 * g) + 547.0 * g * g) / 240.0;
+    }
+}
+
+void orc_weno_smoothness(int order, const double* v, double* beta) { weno_smoothness(order, v, beta); }
+
 double orc_weno_left(int order, double eps, const double* v)
 {
     /* v holds the 2r-1 values v_{i-r+1} .. v_{i+r-1}; returns v at i+1/2 */
+    double b[4];
     if (order == 1) return v[0];
+    weno_smoothness(order, v, b);
     if (order == 3) {
         double vm = v[0], v0 = v[1], vp = v[2];
         double q0 = 0.5 * (-vm + 3.0 * v0);
         double q1 = 0.5 * (v0 + vp);
-        double b0 = (v0 - vm) * (v0 - vm);
-        double b1 = (vp - v0) * (vp - v0);
-        double a0 = (1.0 / 3.0) / ((eps + b0) * (eps + b0));
-        double a1 = (2.0 / 3.0) / ((eps + b1) * (eps + b1));
+        double a0 = (1.0 / 3.0) / ((eps + b[0]) * (eps + b[0]));
+        double a1 = (2.0 / 3.0) / ((eps + b[1]) * (eps + b[1]));
         return (a0 * q0 + a1 * q1) / (a0 + a1);
     }
-    {
+    if (order == 5) {
         double vmm = v[0], vm = v[1], v0 = v[2], vp = v[3], vpp = v[4];
         double q0 = (2.0 * vmm - 7.0 * vm + 11.0 * v0) / 6.0;
         double q1 = (-vm + 5.0 * v0 + 2.0 * vp) / 6.0;
         double q2 = (2.0 * v0 + 5.0 * vp - vpp) / 6.0;
-        double t;
-        double b0, b1, b2;
-        t = vmm - 2.0 * vm + v0; b0 = 13.0 / 12.0 * t * t;
-        t = vmm - 4.0 * vm + 3.0 * v0; b0 += 0.25 * t * t;
-        t = vm - 2.0 * v0 + vp; b1 = 13.0 / 12.0 * t * t;
-        t = vm - vp; b1 += 0.25 * t * t;
-        t = v0 - 2.0 * vp + vpp; b2 = 13.0 / 12.0 * t * t;
-        t = 3.0 * v0 - 4.0 * vp + vpp; b2 += 0.25 * t * t;
-        double a0 = 0.1 / ((eps + b0) * (eps + b0));
-        double a1 = 0.6 / ((eps + b1) * (eps + b1));
-        double a2 = 0.3 / ((eps + b2) * (eps + b2));
+        double a0 = 0.1 / ((eps + b[0]) * (eps + b[0]));
+        double a1 = 0.6 / ((eps + b[1]) * (eps + b[1]));
+        double a2 = 0.3 / ((eps + b[2]) * (eps + b[2]));
         return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+    }
+    {
+        /* order 7: four cubic candidates, linear weights (1, 12, 18, 4)/35 */
+        double q0 = (-3.0 * v[0] + 13.0 * v[1] - 23.0 * v[2] + 25.0 * v[3]) / 12.0;
+        double q1 = (v[1] - 5.0 * v[2] + 13.0 * v[3] + 3.0 * v[4]) / 12.0;
+        double q2 = (-v[2] + 7.0 * v[3] + 7.0 * v[4] - v[5]) / 12.0;
+        double q3 = (3.0 * v[3] + 13.0 * v[4] - 5.0 * v[5] + v[6]) / 12.0;
+        double a0 = (1.0 / 35.0) / ((eps + b[0]) * (eps + b[0]));
+        double a1 = (12.0 / 35.0) / ((eps + b[1]) * (eps + b[1]));
+        double a2 = (18.0 / 35.0) / ((eps + b[2]) * (eps + b[2]));
+        double a3 = (4.0 / 35.0) / ((eps + b[3]) * (eps + b[3]));
+        return (a0 * q0 + a1 * q1 + a2 * q2 + a3 * q3) / (a0 + a1 + a2 + a3);
     }
 }
 
@@ -544,7 +588,7 @@ void orc_char_basis(double gamma, double un, double ut1, double ut2,
  * 2r stencil nodes t = 0 .. 2r-1 (node n-r+1+t); conserved vectors are
  * permuted to (rho, rho u_d, rho u_d+1, rho u_d+2, rho E). */
 static void weno_flux_nodes(double gamma, int order, double eps, int r, int d,
-                            double Wn[6][NV], double qn[6][NQ], double F[NV])
+                            double Wn[8][NV], double qn[8][NQ], double F[NV])
 {
     int perm[NV] = {0, 1 + d, 1 + (d + 1) % 3, 1 + (d + 2) % 3, 4};
     int iu[3] = {Q_U + d, Q_U + (d + 1) % 3, Q_U + (d + 2) % 3};
@@ -555,8 +599,8 @@ static void weno_flux_nodes(double gamma, int order, double eps, int r, int d,
     double ut2 = (sa * qn[A][iu[2]] + sb * qn[B][iu[2]]) / (sa + sb);
     double Hb = (sa * qn[A][Q_H] + sb * qn[B][Q_H]) / (sa + sb);
     double Rm[25], Lm[25];
-    double g[6][NV], qc[6][NV], lam[NV];
-    double gp[6][NV], gm[6][NV];
+    double g[8][NV], qc[8][NV], lam[NV];
+    double gp[8][NV], gm[8][NV];
     double Fc[NV];
     int t, k, v, m;
     orc_char_basis(gamma, un, ut1, ut2, Hb, Rm, Lm);
@@ -590,7 +634,7 @@ static void weno_flux_nodes(double gamma, int order, double eps, int r, int d,
             gm[t][k] = 0.5 * (g[t][k] - lam[k] * qc[t][k]);
         }
     for (k = 0; k < NV; ++k) {
-        double vl[5], vr[5];
+        double vl[7], vr[7];
         /* g+ : nodes i-r+1 .. i+r-1 (positions 0 .. 2r-2) */
         for (t = 0; t < 2 * r - 1; ++t) vl[t] = gp[t][k];
         /* g- : mirrored, nodes i+r .. i-r+2 (positions 2r-1 .. 1) */
@@ -625,7 +669,7 @@ void orc_face_flux_1d(double gamma, int central_order, int weno_order,
         central_flux_line(central_order / 2, a, 0, rho, u, vv, w, pr, H, 3, 1, F);
     } else {
         int r = (weno_order + 1) / 2;
-        double Wn[6][NV], qn[6][NQ];
+        double Wn[8][NV], qn[8][NQ];
         for (t = 0; t < 2 * r; ++t) {
             int src = 3 - r + 1 + t;
             for (v = 0; v < NV; ++v) Wn[t][v] = W1d[src * NV + v];
@@ -645,7 +689,7 @@ static void face_flux(const ctx* c, const double* W, int d, long n, int use_weno
                           Q + Q_V * c->nvol, Q + Q_W * c->nvol, Q + Q_P * c->nvol,
                           Q + Q_H * c->nvol, n, s, F);
     } else {
-        double Wn[6][NV], qn[6][NQ];
+        double Wn[8][NV], qn[8][NQ];
         int t, v;
         for (t = 0; t < 2 * c->r; ++t) {
             long m = n + (t - c->r + 1) * s;

@@ -33,7 +33,7 @@ typedef struct {
     int bc[6];              /* x-lo, x-hi, y-lo, y-hi, z-lo, z-hi */
     double gamma, mach, reynolds, prandtl, visc_exp, t_wall;
     int central_order;      /* 2,4,6,8 */
-    int weno_order;         /* 1,3,5 */
+    int weno_order;         /* 1,3,5,7 */
     int visc_order;         /* 2,4,6,8 */
     int sensor;             /* 0 off, 1 Ducros */
     double sensor_thr, sensor_eps, weno_eps;
@@ -63,6 +63,7 @@ int    orc_num_threads(void);
 /* 1-D building blocks exposed for the pin tests. */
 void   orc_fd_coeffs(int order, double* a, double* b);
 double orc_weno_left(int order, double eps, const double* v);
+void   orc_weno_smoothness(int order, const double* v, double* beta);
 void   orc_char_basis(double gamma, double un, double ut1, double ut2,
                       double H, double* Rm, double* Lm);
 void   orc_face_flux_1d(double gamma, int central_order, int weno_order,

@@ -37,7 +37,7 @@ def _case(n=(16, 14, 12), **kw):
 # ---------------------------------------------------------------------------
 # face-flag window
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("weno_order", [1, 3, 5])
+@pytest.mark.parametrize("weno_order", [1, 3, 5, 7])
 def test_single_hot_sensor_node_flags_exactly_its_stencil_faces(weno_order):
     """Face f of a line (between nodes f-1 and f) is WENO iff a node of its
     stencil f-r .. f+r-1 exceeds the threshold: a single hot node m flags
@@ -166,7 +166,7 @@ def _reference_char_weno_flux(W6, order, gamma, eps):
     return Rv @ Fh
 
 
-@pytest.mark.parametrize("weno_order", [3, 5])
+@pytest.mark.parametrize("weno_order", [3, 5, 7])
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_char_weno_flux_with_fastest_node_at_stencil_end(weno_order, seed):
     """The oracle's characteristic WENO face flux equals the independent
@@ -298,13 +298,14 @@ def _sod_run(nx, weno_order=5, t_end=0.2):
     return xc, Wi
 
 
-def test_sod_with_weno_everywhere_converges_to_exact_solution():
-    """Sod's problem as a y/z-uniform box, WENO-5 characteristic fluxes on
+@pytest.mark.parametrize("weno_order", [5, 7])
+def test_sod_with_weno_everywhere_converges_to_exact_solution(weno_order):
+    """Sod's problem as a y/z-uniform box, WENO characteristic fluxes on
     every face: density and pressure converge in L1 to the exact solution
     at t = 0.2, and every (y, z) line stays identical bitwise."""
     errs = []
     for nx in (50, 100, 200):
-        xc, Wi = _sod_run(nx)
+        xc, Wi = _sod_run(nx, weno_order)
         ref = exact_riemann((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 1.4, (xc - 0.5) / 0.2)
         for k in range(Wi.shape[1]):
             for j in range(Wi.shape[2]):
@@ -373,3 +374,75 @@ def test_compute_dt_viscous_limit_of_resting_gas():
     rate = 3.0 * c / h + 2.0 * 1.4 * mu / (1.5 * 0.72) * 3.0 / (h * h)
     assert rate > 10 * 3.0 * c / h          # the viscous part dominates
     assert o.compute_dt(W, 0.5) == pytest.approx(0.5 / rate, rel=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# WENO-7 (Balsara-Shu) and the smoothness indicators of every order
+# ---------------------------------------------------------------------------
+def _cell_average_poly(vals, offs):
+    """Coefficients (ascending powers of x) of the polynomial of degree
+    len(vals)-1 whose averages over the unit cells centred at `offs` are
+    `vals` (the reconstruction polynomial of a WENO stencil)."""
+    n = len(vals)
+    A = np.array([[((o + 0.5) ** (m + 1) - (o - 0.5) ** (m + 1)) / (m + 1) for m in range(n)] for o in offs])
+    return np.linalg.solve(A, np.asarray(vals, dtype=float))
+
+
+def _smoothness_from_definition(c):
+    """sum_{l>=1} integral over [-1/2, 1/2] of (d^l p / dx^l)^2 (unit h)."""
+    P = np.polynomial.Polynomial(c)
+    tot = 0.0
+    for l in range(1, len(c)):
+        d = P.deriv(l)
+        q = (d * d).integ()
+        tot += q(0.5) - q(-0.5)
+    return tot
+
+
+@pytest.mark.parametrize("order", [3, 5, 7])
+def test_smoothness_indicators_match_their_definition(order):
+    r = (order + 1) // 2
+    rng = np.random.default_rng(order)
+    for _ in range(20):
+        v = rng.normal(size=2 * r - 1)
+        beta = O.weno_smoothness(order, v)
+        for k in range(r):
+            offs = list(range(-r + 1 + k, k + 1))
+            c = _cell_average_poly(v[k:k + r], offs)
+            ref = _smoothness_from_definition(c)
+            assert beta[k] == pytest.approx(ref, rel=1e-11, abs=1e-12 * np.abs(v).max() ** 2)
+
+
+def test_weno7_linear_weights_limit_is_the_seventh_order_reconstruction():
+    """With equal nonlinear weights WENO-7 returns the value at the face of
+    the degree-6 polynomial with the seven given cell averages."""
+    rng = np.random.default_rng(7)
+    for _ in range(10):
+        v = rng.normal(size=7)
+        c = _cell_average_poly(v, list(range(-3, 4)))
+        ref = np.polynomial.Polynomial(c)(0.5)
+        assert O.weno_left(7, 1e30, v) == pytest.approx(ref, rel=1e-12, abs=1e-13)
+
+
+@pytest.mark.parametrize("eps,ns,expect", [
+    (1e30, (32, 64, 128), 6.9),       # linear weights: exactly seventh order
+    (1e-6, (32, 64, 128), 6.5),       # smoothness-weighted: the order holds
+])
+def test_weno7_reconstruction_order_on_smooth_data(eps, ns, expect):
+    r = 4
+    errs = []
+    for n in ns:
+        h = TWO_PI / n
+        x = np.arange(n) * h
+        f = np.sin(x) + 0.3 * np.cos(2 * x)
+        fh = np.array([O.weno_left(7, eps, np.roll(f, -(i - r + 1))[:2 * r - 1]) for i in range(n)])
+        d = (fh - np.roll(fh, 1)) / h
+        errs.append(np.abs(d - (np.cos(x) - 0.6 * np.sin(2 * x))).max())
+    assert math.log2(errs[1] / errs[2]) > expect, errs
+
+
+def test_weno7_is_nonoscillatory_at_a_step():
+    v = np.array([1.0, 1.0, 1.0, 1.0, 0.0, 0.0, 0.0])
+    out = O.weno_left(7, 1e-6, v)
+    assert -1e-9 <= out <= 1.0 + 1e-9
+    assert out == pytest.approx(1.0, abs=1e-3)
