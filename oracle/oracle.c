@@ -480,7 +480,9 @@ static void central_flux_line(int L, const double* a, int d,
  * over derivative orders l = 1..r-1 of the integral over the reconstruction
  * cell of h^(2l-1) (d^l p_k / dx^l)^2, p_k the stencil's reconstruction
  * polynomial). v holds v_{i-r+1} .. v_{i+r-1}. Order 7 is the Balsara-Shu
- * scheme: quadratic forms with denominator 240. */
+ * scheme; its indicators are written as sums of squares of the cubic's
+ * derivatives (the same quadratic forms as the published ones with
+ * denominator 240, without their cancellation on smooth data). */
 static void weno_smoothness(int order, const double* v, double* beta)
 {
     double t;
@@ -497,19 +499,21 @@ static void weno_smoothness(int order, const double* v, double* beta)
         t = v0 - 2.0 * vp + vpp; beta[2] = 13.0 / 12.0 * t * t;
         t = 3.0 * v0 - 4.0 * vp + vpp; beta[2] += 0.25 * t * t;
     } else if (order == 7) {
-        double a = v[0], b = v[1], c = v[2], d = v[3], e = v[4], f = v[5], g = v[6];
-        beta[0] = (a * (547.0 * a - 3882.0 * b + 4642.0 * c - 1854.0 * d)
-                   + b * (7043.0 * b - 17246.0 * c + 7042.0 * d)
-                   + c * (11003.0 * c - 9402.0 * d) + 2107.0 * d * d) / 240.0;
-        beta[1] = (b * (267.0 * b - 1642.0 * c + 1602.0 * d - 494.0 * e)
-                   + c * (2843.0 * c - 5966.0 * d + 1922.0 * e)
-                   + d * (3443.0 * d - 2522.0 * e) + 547.0 * e * e) / 240.0;
-        beta[2] = (c * (547.0 * c - 2522.0 * d + 1922.0 * e - 494.0 * f)
-                   + d * (3443.0 * d - 5966.0 * e + 1602.0 * f)
-                   + e * (2843.0 * e - 1642.0 * f) + 267.0 * f * f) / 240.0;
-        beta[3] = (d * (2107.0 * d - 9402.0 * e + 7042.0 * f - 1854.0 * g)
-                   + e * (11003.0 * e - 17246.0 * f + 4642.0 * g)
-                   + f * (7043.0 * f - 3882.0 * g) + 547.0 * g * g) / 240.0;
+        /* beta_k = s1^2 + 13/3 s2^2 + 781/20 s3^2 with s1 = p' + p'''/24,
+         * s2 = p''/2 and s3 = p'''/6 at the centre of the reconstruction
+         * cell of stencil k's cubic p (unit spacing) */
+        int k;
+        static const double S1[4][4] = {{-2.0, 9.0, -18.0, 11.0}, {1.0, -6.0, 3.0, 2.0},
+                                        {-2.0, -3.0, 6.0, -1.0}, {-11.0, 18.0, -9.0, 2.0}};
+        static const double S2[4][4] = {{-1.0, 4.0, -5.0, 2.0}, {0.0, 1.0, -2.0, 1.0},
+                                        {1.0, -2.0, 1.0, 0.0}, {2.0, -5.0, 4.0, -1.0}};
+        for (k = 0; k < 4; ++k) {
+            const double* w = v + k;
+            double s1 = (S1[k][0] * w[0] + S1[k][1] * w[1] + S1[k][2] * w[2] + S1[k][3] * w[3]) / 6.0;
+            double s2 = (S2[k][0] * w[0] + S2[k][1] * w[1] + S2[k][2] * w[2] + S2[k][3] * w[3]) / 2.0;
+            double s3 = (-w[0] + 3.0 * w[1] - 3.0 * w[2] + w[3]) / 6.0;
+            beta[k] = s1 * s1 + 13.0 / 3.0 * s2 * s2 + 781.0 / 20.0 * s3 * s3;
+        }
     }
 }
 
