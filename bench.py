@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--reps", type=int, default=5,
+                    help="repetitions of the K timed steps; the median one is reported")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle timing (profiling runs)")
     ap.add_argument("--cpu-sample-steps", type=int, default=4)
@@ -108,27 +110,61 @@ def load_flops(kernel: str):
         return None
 
 
-def cpu_baseline(case, Wn, dt, steps):
-    """The oracle, as is, timed on this host on RK3 steps of the same grid."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(case, Wn, dt, steps, single_nz=32, single_steps=2):
+    """The oracle, as is, timed on this host: `steps` RK3 steps of the full
+    grid on all OpenMP threads, and (single-thread rate) `single_steps` RK3
+    steps of a z-slab of the same flow (same x-y planes, single_nz planes,
+    periodic in z like the full block)."""
+    import dataclasses
     import numpy as np
     import oracle as O
+    from paper_2304_05494_amd import inputs
     p = O.Params(**{k: getattr(case, k) for k in O.Params.__dataclass_fields__})
     o = O.Oracle(p)
     W = Wn.copy()
     Rp = np.zeros((5, case.nz, case.ny, case.nx))
+    cores = O.num_threads()
     t0 = time.perf_counter()
     for _ in range(steps):
         o.rk3_step(W, Rp, dt)
     el = time.perf_counter() - t0
+    del W, Rp
+    slab = dataclasses.replace(case, nz=single_nz)
+    ps = O.Params(**{k: getattr(slab, k) for k in O.Params.__dataclass_fields__})
+    os_ = O.Oracle(ps)
+    Ws = np.ascontiguousarray(inputs.fields(slab))
+    Rs = np.zeros((5, slab.nz, slab.ny, slab.nx))
+    O.set_num_threads(1)
+    try:
+        t1 = time.perf_counter()
+        for _ in range(single_steps):
+            os_.rk3_step(Ws, Rs, dt)
+        el1 = time.perf_counter() - t1
+    finally:
+        O.set_num_threads(cores)
     return {"value": case.points * steps / el, "unit": "grid-point updates/s per RK3 step",
-            "cores": O.num_threads(), "kind": "oracle",
+            "cores": cores, "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"{steps} RK3 step(s) of the full {case.nx}x{case.ny}x{case.nz} workload "
-                      f"({el:.1f} s, OpenMP over z-planes)"}
+                      f"({el:.1f} s, OpenMP over z-planes, {cores} threads)",
+            "single_thread": {"value": slab.points * single_steps / el1, "cores": 1,
+                              "sample": f"{single_steps} RK3 step(s) of a {slab.nx}x{slab.ny}x{slab.nz} "
+                                        f"z-slab of the same flow ({el1:.1f} s, one thread)"}}
 
 
-def time_steps(h, dt, steps, warmup):
+def time_steps(h, dt, steps, warmup, reps=3):
     """Wall time per RK3 step (HIP events on the bound stream) and the
-    per-launch time of the fused RHS/update kernel."""
+    per-launch time of the fused RHS/update kernel: the median of `reps`
+    repetitions of `steps` steps."""
     import torch
     for _ in range(warmup):
         h.sx_rk3_step(dt)
@@ -136,14 +172,18 @@ def time_steps(h, dt, steps, warmup):
     h.sx_timing_enable(True)
     h.sx_timing_read()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    start.record()
-    for _ in range(steps):
-        h.sx_rk3_step(dt)
-    stop.record()
-    torch.cuda.synchronize()
-    n, kms = h.sx_timing_read()
+    res = []
+    for _ in range(reps):
+        start.record()
+        for _ in range(steps):
+            h.sx_rk3_step(dt)
+        stop.record()
+        torch.cuda.synchronize()
+        n, kms = h.sx_timing_read()
+        res.append((start.elapsed_time(stop) / steps, kms / n))
     h.sx_timing_enable(False)
-    return start.elapsed_time(stop) / steps, kms / n
+    res.sort()
+    return res[len(res) // 2]
 
 
 def bench_tgv(args):
@@ -355,20 +395,26 @@ def main():
         h.sx_rk3_step(dt)
     torch.cuda.synchronize()
 
+    # REPS repetitions of K timed steps; the median repetition is reported
     h.sx_timing_enable(True)
     h.sx_timing_read()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    start.record()
-    for _ in range(args.steps):
-        h.sx_rk3_step(dt)
-    stop.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_total = start.elapsed_time(stop)
-    launches, kern_ms = h.sx_timing_read()
+    reps = []
+    wall = 0.0
+    for _ in range(args.reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        start.record()
+        for _ in range(args.steps):
+            h.sx_rk3_step(dt)
+        stop.record()
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
+        n_l, k_ms = h.sx_timing_read()
+        reps.append((start.elapsed_time(stop), n_l, k_ms))
     h.sx_timing_enable(False)
+    reps.sort(key=lambda r: r[0])
+    ms_total, launches, kern_ms = reps[len(reps) // 2]
 
     d = h.sx_diagnostics()
     ok = d.status == sx.SX_OK
@@ -417,6 +463,8 @@ def main():
             "alg_bytes_per_launch": alg_bytes_launch,
         },
         "state_ok": ok,
+        "timing": f"median of {args.reps} repetitions of {args.steps} steps (HIP events on the bound stream)",
+        "ms_per_step_reps": [r[0] / args.steps for r in reps],
         "wall_s_timed": wall,
     }
     fl = load_flops(kernel)
@@ -430,26 +478,15 @@ def main():
     h32 = sx.Handle(case, precision=sx.SX_FP32_FLUX)
     W32 = h32.to_layout(Wn)
     h32.sx_bind(W32)
-    for _ in range(args.warmup):
-        h32.sx_rk3_step(dt)
-    torch.cuda.synchronize()
-    h32.sx_timing_enable(True)
-    h32.sx_timing_read()
-    start.record()
-    for _ in range(args.steps):
-        h32.sx_rk3_step(dt)
-    stop.record()
-    torch.cuda.synchronize()
-    ms32 = start.elapsed_time(stop) / args.steps
-    n32, k32 = h32.sx_timing_read()
+    ms32, l32 = time_steps(h32, dt, args.steps, args.warmup, args.reps)
     fl32 = load_flops("k_rhs_central<3, 64, 8, 2, float, true, false, false>")
     line["fp32_flux"] = {
-        "valu_fp32_tflops": None if fl32 is None else fl32["fp32_flops_per_launch"] / (k32 / n32 * 1e-3) / 1e12,
+        "valu_fp32_tflops": None if fl32 is None else fl32["fp32_flops_per_launch"] / (l32 * 1e-3) / 1e12,
         "value": case.points / (ms32 * 1e-3),
         "ms_per_step": ms32,
         "speedup_vs_fp64": ms_per_step / ms32,
-        "launch_ms": k32 / n32,
-        "roofline_frac": ALG_BYTES_PER_POINT_STEP / SUBSTEPS * case.points / (k32 / n32 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "launch_ms": l32,
+        "roofline_frac": ALG_BYTES_PER_POINT_STEP / SUBSTEPS * case.points / (l32 * 1e-3) / 1e9 / HBM_PEAK_GBS,
     }
     del h32, W32
     if not args.no_batch:

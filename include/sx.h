@@ -193,6 +193,15 @@ int sx_diagnostics(sx_handle* h, const double* R, sx_diag* out);
 int sx_set_flag_override(sx_handle* h, const unsigned char* fx, const unsigned char* fy,
                          const unsigned char* fz);
 
+/* Face flags of the last hybrid evaluation on this handle (the sensor's, or
+ * the injected ones): the switch of Section 2 that selects WENO fluxes on a
+ * face. Written by sx_rhs, by every substep of sx_rk3_step (the last one
+ * wins) and by sx_diagnostics; all zero before the first. Same layouts as
+ * sx_set_flag_override (fx [nz][ny][nx+1], fy [nz][ny+1][nx],
+ * fz [nz+1][ny][nx], 1 = WENO); host or device pointers owned by the
+ * caller. Synchronises the stream. SX_ESTATE if the sensor is off. */
+int sx_get_flags(sx_handle* h, unsigned char* fx, unsigned char* fy, unsigned char* fz);
+
 /* Kernel timing for measurement. When enabled, sx_rk3_step brackets every
  * launch of the fused right-hand-side/update kernel with HIP events recorded
  * on the bound stream. sx_timing_read synchronises the recorded events,
@@ -205,9 +214,11 @@ int sx_timing_read(sx_handle* h, long long* launches, double* total_ms);
  * Many independent blocks of uneven size advanced together: one persistent
  * launch per RK3 substep works through a list of (block, column tile,
  * z-chunk) work items, and the three substeps of a step are captured in a
- * HIP graph that sx_rk3_step replays. This is the throughput analogue of the
- * paper's many-block-per-device runs and of its launch-shape tuning
- * (Sections 3.3-3.4); every block follows the single-block equations.
+ * HIP graph that sx_rk3_step replays. The paper runs one block per GPU; the
+ * autotuned work-item shape is the counterpart of its launch-bound and
+ * thread-block tuning (Section 4.1, Table 3) and of the per-kernel launch
+ * settings its translation tool reads from a configuration file (Section
+ * 3.3). Every block follows the single-block equations.
  *
  * Every block must be periodic on all six faces (the kernel writes the
  * periodic ghost images, so no ghost-fill launches sit between substeps),

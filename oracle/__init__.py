@@ -115,6 +115,7 @@ def lib():
         L.orc_compute_dt.restype = ctypes.c_double
         L.orc_diagnostics.argtypes = [P, dp, dp, dp]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
         L.orc_fd_coeffs.argtypes = [ctypes.c_int, dp, dp]
         L.orc_weno_left.argtypes = [ctypes.c_int, ctypes.c_double, dp]
         L.orc_weno_left.restype = ctypes.c_double
@@ -270,3 +271,8 @@ def face_flux_1d(gamma, W8, central_order=6, weno_order=5, weno_eps=1e-6, use_we
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP thread count of later oracle calls."""
+    lib().orc_set_num_threads(int(n))

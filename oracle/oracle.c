@@ -1094,6 +1094,15 @@ void orc_diagnostics(const orc_params* p, double* W, const double* R, double* ou
 }
 
 /* Threads the OpenMP loops of this oracle use (1 without OpenMP). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

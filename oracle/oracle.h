@@ -59,6 +59,7 @@ void   orc_diagnostics(const orc_params* p, double* W, const double* R,
                        double* out);
 
 int    orc_num_threads(void);
+void   orc_set_num_threads(int n);   /* OpenMP threads of later calls */
 
 /* 1-D building blocks exposed for the pin tests. */
 void   orc_fd_coeffs(int order, double* a, double* b);

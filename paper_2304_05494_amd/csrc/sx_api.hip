@@ -238,6 +238,7 @@ int sx_init(const sx_grid* grid, const sx_gas* gas, const sx_scheme* scheme, sx_
         e = hipMalloc(&b.theta, sizeof(double) * ni);
         for (int d = 0; d < 3 && e == hipSuccess; ++d) {
             e = hipMalloc(&b.f[d], (size_t)nf[d]);
+            if (e == hipSuccess) e = hipMemset(b.f[d], 0, (size_t)nf[d]);
             if (e == hipSuccess) e = hipMalloc(&b.flist[d], sizeof(int) * nf[d]);
             if (e == hipSuccess) e = hipMalloc(&b.dF[d], sizeof(double) * sx::NV * nf[d]);
         }
@@ -471,6 +472,22 @@ int sx_set_flag_override(sx_handle* h, const unsigned char* fx, const unsigned c
     if (e == hipSuccess) e = hipStreamSynchronize(h->st);
     if (e != hipSuccess) return sx_hip_fail(h, e, "sx_set_flag_override");
     h->flag_override = 1;
+    return SX_OK;
+}
+
+int sx_get_flags(sx_handle* h, unsigned char* fx, unsigned char* fy, unsigned char* fz)
+{
+    if (!h) return SX_EINVAL;
+    if (!h->ks.sensor || h->batch) return sx_fail(h, SX_ESTATE, "sx_get_flags: sensor is off");
+    if (!fx || !fy || !fz) return sx_fail(h, SX_EINVAL, "sx_get_flags: need all three arrays");
+    const sx_grid& g = h->grid;
+    hipError_t e = hipMemcpyAsync(fx, h->wb.f[0], (size_t)g.nz * g.ny * (g.nx + 1), hipMemcpyDefault, h->st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(fy, h->wb.f[1], (size_t)g.nz * (g.ny + 1) * g.nx, hipMemcpyDefault, h->st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(fz, h->wb.f[2], (size_t)(g.nz + 1) * g.ny * g.nx, hipMemcpyDefault, h->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+    if (e != hipSuccess) return sx_hip_fail(h, e, "sx_get_flags");
     return SX_OK;
 }
 

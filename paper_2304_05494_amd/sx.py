@@ -77,6 +77,7 @@ class sx_tiling(ctypes.Structure):
 
 EXPORTS = ["sx_init", "sx_finalize", "sx_get_layout", "sx_bind", "sx_current", "sx_fill_ghosts",
            "sx_rhs", "sx_rk3_step", "sx_compute_dt", "sx_diagnostics", "sx_set_flag_override",
+           "sx_get_flags",
            "sx_timing_enable", "sx_timing_read", "sx_init_batch", "sx_get_box", "sx_set_tiling",
            "sx_get_tiling", "sx_autotune", "sx_set_graph", "sx_last_error"]
 
@@ -107,6 +108,7 @@ def load() -> ctypes.CDLL:
     L.sx_compute_dt.argtypes = [H, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
     L.sx_diagnostics.argtypes = [H, dp, ctypes.POINTER(sx_diag)]
     L.sx_set_flag_override.argtypes = [H, dp, dp, dp]
+    L.sx_get_flags.argtypes = [H, dp, dp, dp]
     L.sx_timing_enable.argtypes = [H, ctypes.c_int]
     L.sx_timing_read.argtypes = [H, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double)]
     L.sx_init_batch.argtypes = [ctypes.c_int, ctypes.POINTER(sx_grid), ctypes.POINTER(sx_gas),
@@ -251,6 +253,15 @@ class Handle:
         import numpy as _np
         arrs = [_np.ascontiguousarray(f, dtype=_np.uint8) for f in flags]
         self._check(self.lib.sx_set_flag_override(self.h, *[a.ctypes.data for a in arrs]))
+
+    def sx_get_flags(self):
+        """Face flags of the last hybrid evaluation as numpy uint8 arrays
+        (fx [nz][ny][nx+1], fy [nz][ny+1][nx], fz [nz+1][ny][nx])."""
+        c = self.case
+        out = [np.zeros((c.nz, c.ny, c.nx + 1), np.uint8), np.zeros((c.nz, c.ny + 1, c.nx), np.uint8),
+               np.zeros((c.nz + 1, c.ny, c.nx), np.uint8)]
+        self._check(self.lib.sx_get_flags(self.h, *[a.ctypes.data for a in out]))
+        return out
 
     def sx_timing_enable(self, enable: bool = True):
         self._check(self.lib.sx_timing_enable(self.h, int(enable)))

@@ -65,13 +65,12 @@ def rhs_scale(ref):
 def assert_rhs_close(got, ref, tol, floor=None):
     """Per conserved variable max|got-ref| over max|ref| (momentum on the
     shared momentum scale, so a component that vanishes identically, like w
-    in the Taylor-Green vortex, is compared on that scale). `floor` bounds
-    the denominators from below: a single term whose exact value is zero
-    (a z-derivative of the Nyquist mode of a 4-point direction) is then
-    compared on the scale of the whole right-hand side."""
+    in the Taylor-Green vortex, is compared on that scale). `floor`, where
+    given, replaces the denominator of a variable whose term is zero in
+    exact arithmetic and only rounding noise in the oracle."""
     scale = rhs_scale(ref)
     if floor is not None:
-        scale = np.maximum(scale, floor)
+        scale = np.where(floor > 0, floor, scale)
     for v in range(5):
         if scale[v] == 0.0:
             assert np.abs(got[v]).max() == 0.0
@@ -114,8 +113,16 @@ def test_rhs_term_parity(case, mask):
     got = R.cpu().numpy()
     o = oracle_for(case)
     ref = o.rhs(Wn.copy(), mask=mask)
-    floor = rhs_scale(o.rhs(Wn.copy(), mask=sx.SX_ALL))
-    assert_rhs_close(got, ref, 1e-11, floor)
+    # Every term is compared on its own scale, except a term that vanishes in
+    # exact arithmetic (the z-derivative of a Nyquist mode on a 4-point
+    # periodic direction, which the oracle returns as ~1e-15 of the whole
+    # right-hand side): that one is compared on the whole right-hand side's
+    # scale.
+    full = rhs_scale(o.rhs(Wn.copy(), mask=sx.SX_ALL))
+    term = rhs_scale(ref)
+    noise = (term > 0) & (term <= 1e-12 * full)
+    assert not noise.any() or case.name == "tgv-c6-min4", (case.name, term / full)
+    assert_rhs_close(got, ref, 1e-11, np.where(noise, full, 0.0))
 
 
 BY_NAME = {c.name: c for c in CASES}
