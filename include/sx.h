@@ -91,8 +91,9 @@ typedef struct {
 
 typedef struct {
     int central_order;        /* 2, 4, 6, 8 */
-    int weno_order;           /* 1, 3, 5 */
-    int visc_order;           /* must equal central_order in this build */
+    int weno_order;           /* 1, 3, 5, 7 */
+    int visc_order;           /* 2, 4, 6, 8 (independent of central_order; the
+                                 batched form needs them equal) */
     int sensor;               /* 0 off (pure central), 1 Ducros hybrid; the hybrid
                                  allocates at sx_init the sensor, face flags,
                                  face and node lists and the per-face WENO
@@ -238,7 +239,8 @@ int sx_timing_read(sx_handle* h, long long* launches, double* total_ms);
  *                  sums and counts, max/min over blocks of the extrema.
  * With timing on, each recorded interval spans one whole step (three
  * substep launches) and sx_timing_read counts three launches per step.
- * Returns SX_EUNSUPPORTED for non-periodic blocks, a sensor, or blocks
+ * Returns SX_EUNSUPPORTED for non-periodic blocks, a sensor, unequal
+ * convective and viscous orders, or blocks
  * smaller than twice the ghost width; SX_EINVAL for other bad input. */
 int sx_init_batch(int nbox, const sx_grid* grids, const sx_gas* gases, const sx_scheme* scheme,
                   sx_handle** out);

@@ -99,8 +99,7 @@ void sx_host_metrics(const sx_grid& g, int L, double* y_eta, double* y_ee)
 int sx_validate(const sx_grid& g, const sx_gas& gas, const sx_scheme& s, int* ng_out)
 {
     if (!valid_order(s.central_order) || !valid_order(s.visc_order)) return SX_EINVAL;
-    if (s.weno_order != 1 && s.weno_order != 3 && s.weno_order != 5) return SX_EINVAL;
-    if (s.visc_order != s.central_order) return SX_EUNSUPPORTED;
+    if (s.weno_order != 1 && s.weno_order != 3 && s.weno_order != 5 && s.weno_order != 7) return SX_EINVAL;
     if (s.sensor != 0 && s.sensor != 1) return SX_EINVAL;
     if (s.precision != SX_FP64 && s.precision != SX_FP32_FLUX) return SX_EINVAL;
     if (!(gas.gamma > 1.0) || !(gas.mach > 0.0) || !(gas.reynolds > 0.0) || !(gas.prandtl > 0.0))
@@ -225,7 +224,8 @@ int sx_init(const sx_grid* grid, const sx_gas* gas, const sx_scheme* scheme, sx_
     }
     bool all_periodic = true;
     for (int f = 0; f < 6; ++f) all_periodic = all_periodic && g.bc[f] == SX_BC_PERIODIC;
-    h->pimg = all_periodic && !s.sensor && g.nx >= 2 * ng && g.ny >= 2 * ng && g.nz >= 2 * ng;
+    h->pimg = all_periodic && !s.sensor && s.visc_order == s.central_order && g.nx >= 2 * ng &&
+              g.ny >= 2 * ng && g.nz >= 2 * ng;
 
     hipError_t e = sx_upload_metrics(g, h->ks.L, &h->d_metrics, &h->kg);
     if (e == hipSuccess)

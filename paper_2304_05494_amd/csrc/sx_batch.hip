@@ -404,6 +404,8 @@ int sx_init_batch(int nbox, const sx_grid* grids, const sx_gas* gases, const sx_
         if (grids[b].nx < 2 * ngb || grids[b].ny < 2 * ngb || grids[b].nz < 2 * ngb) return SX_EUNSUPPORTED;
         ng = ngb;
     }
+    // the persistent kernels are built for equal convective and viscous orders
+    if (scheme->visc_order != scheme->central_order) return SX_EUNSUPPORTED;
     sx_handle* h = new sx_handle();
     h->batch = true;
     h->scheme = *scheme;

@@ -69,6 +69,24 @@ __device__ __forceinline__ R d1(const R (&f)[2 * S + 1])
     return s;
 }
 
+// First derivative of order 2V centred on entry H of a window of 2H+1
+// values (V <= H).
+template <int V, int H, typename R>
+__device__ __forceinline__ R d1c(const R (&f)[2 * H + 1])
+{
+    R s = R(0);
+#pragma unroll
+    for (int l = 1; l <= V; ++l) s += R(Coef<V>::a[l]) * (f[H + l] - f[H - l]);
+    return s;
+}
+
+// Half-width of the stencils of a kernel: the larger of the convective and
+// viscous half-orders.
+template <int SC, int SV>
+struct Halo {
+    static constexpr int S = SC > SV ? SC : SV;
+};
+
 // Viscosity law T^s: FP64 through exp(s log T); FP32 through the hardware
 // base-2 logarithm and exponential.
 template <typename R>
@@ -235,18 +253,20 @@ __device__ __forceinline__ Node<R> ring_read(const R* z, R igM2)
 // to acc and returns first derivatives gd = (u, v, w, T)_n and the pure
 // second derivatives dd = (u, v, w, T)_nn (sc: metric 1/h or eta_y;
 // sc2 = sc^2; scy = eta_yy along y, 0 otherwise).
-template <int S, int D, bool CONV, bool VISC, typename R, typename Get>
+template <int SC, int SV, int D, bool CONV, bool VISC, typename R, typename Get>
 __device__ __forceinline__ void stencil_dir(Get get, R sc, R sc2, R scy, R (&acc)[NV], R (&gd)[4],
                                             R (&dd)[4])
 {
+    // convective pairs up to SC, viscous differences up to SV
+    constexpr int SL = CONV && VISC ? Halo<SC, SV>::S : (CONV ? SC : SV);
     const Node<R> C = get(0);
     R f0 = 0, f1 = 0, f2 = 0, f3 = 0, f4 = 0, fp = 0;
     R s1[4] = {0, 0, 0, 0}, s2[4] = {0, 0, 0, 0};
 #pragma unroll
-    for (int l = 1; l <= S; ++l) {
+    for (int l = 1; l <= SL; ++l) {
         const Node<R> M = get(-l), P = get(l);
-        if (CONV) {
-            const R cl = R(0.25 * Coef<S>::a[l]);
+        if (CONV && l <= SC) {
+            const R cl = R(0.25 * Coef<SC>::a[l]);
             const R udC = D == 0 ? C.u : (D == 1 ? C.v : C.w);
             const R udP = D == 0 ? P.u : (D == 1 ? P.v : P.w);
             const R udM = D == 0 ? M.u : (D == 1 ? M.v : M.w);
@@ -259,8 +279,8 @@ __device__ __forceinline__ void stencil_dir(Get get, R sc, R sc2, R scy, R (&acc
             f4 += mp * (C.H + P.H) - mm * (M.H + C.H);
             fp += (R(4) * cl) * (P.p - M.p);
         }
-        if (VISC) {
-            const R al = R(Coef<S>::a[l]), bl = R(Coef<S>::b[l]);
+        if (VISC && l <= SV) {
+            const R al = R(Coef<SV>::a[l]), bl = R(Coef<SV>::b[l]);
             s1[0] += al * (P.u - M.u);
             s1[1] += al * (P.v - M.v);
             s1[2] += al * (P.w - M.w);
@@ -343,13 +363,14 @@ __device__ __forceinline__ void sto(T* base, unsigned bo, T v)
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + bo) = v;
 }
 
-template <int S, int TX, int TY, typename R, bool UPD, bool PIMG>
-__device__ __forceinline__ void march(Smem<S, TX, TY, R>& sm, const double* __restrict__ W,
+template <int SC, int SV, int TX, int TY, typename R, bool UPD, bool PIMG>
+__device__ __forceinline__ void march(Smem<Halo<SC, SV>::S, TX, TY, R>& sm, const double* __restrict__ W,
                                       double* __restrict__ out, double* __restrict__ Rp,
                                       const KGrid& g, const KGas& gas, const StepCoef& sc,
                                       unsigned mask_in, int i0, int j0, int k0, int k1)
 {
     const unsigned mask = UPD ? (unsigned)SX_ALL : mask_in;   // an update always takes every term
+    constexpr int S = Halo<SC, SV>::S;
     using L = Layout<R>;
     constexpr int NT = TX * TY;
     constexpr int HX = TX + 2 * S, HY = TY + 2 * S, HP = HX * HY;
@@ -477,17 +498,18 @@ __device__ __forceinline__ void march(Smem<S, TX, TY, R>& sm, const double* __re
     // newest mixed-queue slot from the staged arrival plane
     auto arrive = [&]() {
         if (!active) return;
-        R xw[Q], yw[Q], xu[Q], yv[Q];
+        constexpr int QV = 2 * SV + 1;
+        R xw[QV], yw[QV], xu[QV], yv[QV];
 #pragma unroll
-        for (int t = 0; t < Q; ++t) {
-            xu[t] = sa[0][c + t - S];
-            xw[t] = sa[2][c + t - S];
-            yv[t] = sa[1][c + (t - S) * HX];
-            yw[t] = sa[2][c + (t - S) * HX];
+        for (int t = 0; t < QV; ++t) {
+            xu[t] = sa[0][c + t - SV];
+            xw[t] = sa[2][c + t - SV];
+            yv[t] = sa[1][c + (t - SV) * HX];
+            yw[t] = sa[2][c + (t - SV) * HX];
         }
-        m0[Q - 1] = dxi * d1<S>(xw);
-        m1[Q - 1] = ey * d1<S>(yw);
-        m2[Q - 1] = dxi * d1<S>(xu) + ey * d1<S>(yv);
+        m0[Q - 1] = dxi * d1<SV>(xw);
+        m1[Q - 1] = ey * d1<SV>(yw);
+        m2[Q - 1] = dxi * d1<SV>(xu) + ey * d1<SV>(yv);
     };
     auto shift = [&]() {
 #pragma unroll
@@ -584,10 +606,10 @@ __device__ __forceinline__ void march(Smem<S, TX, TY, R>& sm, const double* __re
         auto gy_at = [&](int hx) {
             R su = 0, sv = 0;
 #pragma unroll
-            for (int l = 1; l <= S; ++l) {
+            for (int l = 1; l <= SV; ++l) {
                 const int up = L::PREC * ((ty + S + l) * HX + hx), dn = L::PREC * ((ty + S - l) * HX + hx);
-                su += R(Coef<S>::a[l]) * (so[up + L::OU] - so[dn + L::OU]);
-                sv += R(Coef<S>::a[l]) * (so[up + L::OV] - so[dn + L::OV]);
+                su += R(Coef<SV>::a[l]) * (so[up + L::OU] - so[dn + L::OU]);
+                sv += R(Coef<SV>::a[l]) * (so[up + L::OV] - so[dn + L::OV]);
             }
             gyl[0][ty][hx] = eyr * su;
             gyl[1][ty][hx] = eyr * sv;
@@ -620,24 +642,24 @@ __device__ __forceinline__ void march(Smem<S, TX, TY, R>& sm, const double* __re
                 return znode(sl);
             };
             if (mask & SX_CONV_X) {
-                if (visc) stencil_dir<S, 0, true, true>(getx, dxi, dxi * dxi, R(0), acc, gx, dd);
-                else stencil_dir<S, 0, true, false>(getx, dxi, dxi * dxi, R(0), acc, gx, dd);
+                if (visc) stencil_dir<SC, SV, 0, true, true>(getx, dxi, dxi * dxi, R(0), acc, gx, dd);
+                else stencil_dir<SC, SV, 0, true, false>(getx, dxi, dxi * dxi, R(0), acc, gx, dd);
             } else if (visc) {
-                stencil_dir<S, 0, false, true>(getx, dxi, dxi * dxi, R(0), acc, gx, dd);
+                stencil_dir<SC, SV, 0, false, true>(getx, dxi, dxi * dxi, R(0), acc, gx, dd);
             }
             if (visc) visc_linear<0>(dd, mu, kcd, uc, vc, wc_, acc);
             if (mask & SX_CONV_Y) {
-                if (visc) stencil_dir<S, 1, true, true>(gety, ey, ey * ey, eyy, acc, gy, dd);
-                else stencil_dir<S, 1, true, false>(gety, ey, ey * ey, eyy, acc, gy, dd);
+                if (visc) stencil_dir<SC, SV, 1, true, true>(gety, ey, ey * ey, eyy, acc, gy, dd);
+                else stencil_dir<SC, SV, 1, true, false>(gety, ey, ey * ey, eyy, acc, gy, dd);
             } else if (visc) {
-                stencil_dir<S, 1, false, true>(gety, ey, ey * ey, eyy, acc, gy, dd);
+                stencil_dir<SC, SV, 1, false, true>(gety, ey, ey * ey, eyy, acc, gy, dd);
             }
             if (visc) visc_linear<1>(dd, mu, kcd, uc, vc, wc_, acc);
             if (mask & SX_CONV_Z) {
-                if (visc) stencil_dir<S, 2, true, true>(getz, dzi, dzi * dzi, R(0), acc, gz, dd);
-                else stencil_dir<S, 2, true, false>(getz, dzi, dzi * dzi, R(0), acc, gz, dd);
+                if (visc) stencil_dir<SC, SV, 2, true, true>(getz, dzi, dzi * dzi, R(0), acc, gz, dd);
+                else stencil_dir<SC, SV, 2, true, false>(getz, dzi, dzi * dzi, R(0), acc, gz, dd);
             } else if (visc) {
-                stencil_dir<S, 2, false, true>(getz, dzi, dzi * dzi, R(0), acc, gz, dd);
+                stencil_dir<SC, SV, 2, false, true>(getz, dzi, dzi * dzi, R(0), acc, gz, dd);
             }
             // enthalpy shift correction of the convective energy flux (FP64)
             const double accE_shift = href * double(acc[0]);
@@ -651,9 +673,9 @@ __device__ __forceinline__ void march(Smem<S, TX, TY, R>& sm, const double* __re
                     gyv[t] = gyl[1][ty][tx + t];
                 }
                 const R m3 = mu * R(1.0 / 3.0);
-                const R mx = m3 * (dxi * d1<S>(gyv) + dzi * d1<S>(m0));   // d_x d_y v + d_z d_x w
-                const R my = m3 * (dxi * d1<S>(gyu) + dzi * d1<S>(m1));   // d_x d_y u + d_z d_y w
-                const R mz = m3 * (dzi * d1<S>(m2));                      // d_z (d_x u + d_y v)
+                const R mx = m3 * (dxi * d1c<SV, S>(gyv) + dzi * d1c<SV, S>(m0));   // d_x d_y v + d_z d_x w
+                const R my = m3 * (dxi * d1c<SV, S>(gyu) + dzi * d1c<SV, S>(m1));   // d_x d_y u + d_z d_y w
+                const R mz = m3 * (dzi * d1c<SV, S>(m2));                      // d_z (d_x u + d_y v)
                 acc[1] += mx;
                 acc[2] += my;
                 acc[3] += mz;
@@ -730,13 +752,14 @@ struct SmemSplit {
 // was last read before barrier 2 of plane k, the hand-over arrays are read
 // by role 0 before it reaches barrier 1 of plane k+1 and written again by
 // role 1 only after it, and the D_y rows are private to one wave.
-template <int S, int TX, int TY, typename R, bool UPD, bool PIMG>
-__device__ __forceinline__ void march_split(SmemSplit<S, TX, TY, R>& sm, const double* __restrict__ W,
+template <int SC, int SV, int TX, int TY, typename R, bool UPD, bool PIMG>
+__device__ __forceinline__ void march_split(SmemSplit<Halo<SC, SV>::S, TX, TY, R>& sm, const double* __restrict__ W,
                                             double* __restrict__ out, double* __restrict__ Rp,
                                             const KGrid& g, const KGas& gas, const StepCoef& sc,
                                             unsigned mask_in, int i0, int j0, int k0, int k1)
 {
     const unsigned mask = UPD ? (unsigned)SX_ALL : mask_in;
+    constexpr int S = Halo<SC, SV>::S;
     using L = Layout<R>;
     constexpr int NR = TX * TY;
     constexpr int HX = TX + 2 * S, HP = HX * (TY + 2 * S);
@@ -910,10 +933,10 @@ __device__ __forceinline__ void march_split(SmemSplit<S, TX, TY, R>& sm, const d
             auto gy_at = [&](int hx) {
                 R su = 0, sv = 0;
 #pragma unroll
-                for (int l = 1; l <= S; ++l) {
+                for (int l = 1; l <= SV; ++l) {
                     const int up = L::PREC * ((ty + S + l) * HX + hx), dn = L::PREC * ((ty + S - l) * HX + hx);
-                    su += R(Coef<S>::a[l]) * (so[up + L::OU] - so[dn + L::OU]);
-                    sv += R(Coef<S>::a[l]) * (so[up + L::OV] - so[dn + L::OV]);
+                    su += R(Coef<SV>::a[l]) * (so[up + L::OU] - so[dn + L::OU]);
+                    sv += R(Coef<SV>::a[l]) * (so[up + L::OV] - so[dn + L::OV]);
                 }
                 gyl[0][ty][hx] = eyr * su;
                 gyl[1][ty][hx] = eyr * sv;
@@ -936,8 +959,8 @@ __device__ __forceinline__ void march_split(SmemSplit<S, TX, TY, R>& sm, const d
                 }
                 const Node<R> Cc = getx(0);
                 const R m3 = vmu[tid] * R(1.0 / 3.0);
-                const R mxy = m3 * (dxi * d1<S>(gyv));
-                const R myx = m3 * (dxi * d1<S>(gyu));
+                const R mxy = m3 * (dxi * d1c<SV, S>(gyv));
+                const R myx = m3 * (dxi * d1c<SV, S>(gyu));
                 acc[1] += mxy;
                 acc[2] += myx;
                 acc[4] += Cc.u * mxy + Cc.v * myx;
@@ -949,9 +972,9 @@ __device__ __forceinline__ void march_split(SmemSplit<S, TX, TY, R>& sm, const d
                     sl = sl < 0 ? sl + Q : (sl >= Q ? sl - Q : sl);
                     return znode(sl);
                 };
-                if (mask & SX_CONV_X) stencil_dir<S, 0, true, false>(getx, dxi, dxi, R(0), acc, gd, dd);
-                if (mask & SX_CONV_Y) stencil_dir<S, 1, true, false>(gety, ey, ey, R(0), acc, gd, dd);
-                if (mask & SX_CONV_Z) stencil_dir<S, 2, true, false>(getz, dzi, dzi, R(0), acc, gd, dd);
+                if (mask & SX_CONV_X) stencil_dir<SC, SV, 0, true, false>(getx, dxi, dxi, R(0), acc, gd, dd);
+                if (mask & SX_CONV_Y) stencil_dir<SC, SV, 1, true, false>(gety, ey, ey, R(0), acc, gd, dd);
+                if (mask & SX_CONV_Z) stencil_dir<SC, SV, 2, true, false>(getz, dzi, dzi, R(0), acc, gd, dd);
             }
             __syncthreads();                                   // 2: viscous part ready
             if (active) {
@@ -992,17 +1015,18 @@ __device__ __forceinline__ void march_split(SmemSplit<S, TX, TY, R>& sm, const d
         };
         auto arrive = [&]() {
             if (!active) return;
-            R xw[Q], yw[Q], xu[Q], yv[Q];
+            constexpr int QV = 2 * SV + 1;
+            R xw[QV], yw[QV], xu[QV], yv[QV];
 #pragma unroll
-            for (int t = 0; t < Q; ++t) {
-                xu[t] = sa[0][c + t - S];
-                xw[t] = sa[2][c + t - S];
-                yv[t] = sa[1][c + (t - S) * HX];
-                yw[t] = sa[2][c + (t - S) * HX];
+            for (int t = 0; t < QV; ++t) {
+                xu[t] = sa[0][c + t - SV];
+                xw[t] = sa[2][c + t - SV];
+                yv[t] = sa[1][c + (t - SV) * HX];
+                yw[t] = sa[2][c + (t - SV) * HX];
             }
-            m0[Q - 1] = dxi * d1<S>(xw);
-            m1[Q - 1] = ey * d1<S>(yw);
-            m2[Q - 1] = dxi * d1<S>(xu) + ey * d1<S>(yv);
+            m0[Q - 1] = dxi * d1<SV>(xw);
+            m1[Q - 1] = ey * d1<SV>(yw);
+            m2[Q - 1] = dxi * d1<SV>(xu) + ey * d1<SV>(yv);
         };
         auto shift = [&]() {
 #pragma unroll
@@ -1072,18 +1096,18 @@ __device__ __forceinline__ void march_split(SmemSplit<S, TX, TY, R>& sm, const d
                     sl = sl < 0 ? sl + Q : (sl >= Q ? sl - Q : sl);
                     return znode(sl);
                 };
-                stencil_dir<S, 0, false, true>(getx, dxi, dxi * dxi, R(0), acc, gx, dd);
+                stencil_dir<SC, SV, 0, false, true>(getx, dxi, dxi * dxi, R(0), acc, gx, dd);
                 visc_linear<0>(dd, mu, kcd, uc, vc, wc_, acc);
-                stencil_dir<S, 1, false, true>(gety, ey, ey * ey, eyy, acc, gy, dd);
+                stencil_dir<SC, SV, 1, false, true>(gety, ey, ey * ey, eyy, acc, gy, dd);
                 visc_linear<1>(dd, mu, kcd, uc, vc, wc_, acc);
-                stencil_dir<S, 2, false, true>(getz, dzi, dzi * dzi, R(0), acc, gz, dd);
+                stencil_dir<SC, SV, 2, false, true>(getz, dzi, dzi * dzi, R(0), acc, gz, dd);
                 visc_linear<2>(dd, mu, kcd, uc, vc, wc_, acc);
                 // mixed z parts of mu/3 d_i(div u): d_z d_x w, d_z d_y w,
                 // d_z (d_x u + d_y v) (the x-y parts are the convective role's)
                 const R m3 = mu * R(1.0 / 3.0);
-                const R mx = m3 * (dzi * d1<S>(m0));
-                const R my = m3 * (dzi * d1<S>(m1));
-                const R mz = m3 * (dzi * d1<S>(m2));
+                const R mx = m3 * (dzi * d1c<SV, S>(m0));
+                const R my = m3 * (dzi * d1c<SV, S>(m1));
+                const R mz = m3 * (dzi * d1c<SV, S>(m2));
                 acc[1] += mx;
                 acc[2] += my;
                 acc[3] += mz;
@@ -1125,20 +1149,20 @@ struct SmemOf<S, TX, TY, R, true> {
     using type = SmemSplit<S, TX, TY, R>;
 };
 
-template <int S, int TX, int TY, int WPE, typename R, bool UPD, bool PIMG, bool SPLIT>
+template <int SC, int SV, int TX, int TY, int WPE, typename R, bool UPD, bool PIMG, bool SPLIT>
 __global__ void __attribute__((amdgpu_flat_work_group_size(TX * TY * (SPLIT ? 2 : 1), TX * TY * (SPLIT ? 2 : 1)),
                                amdgpu_waves_per_eu(WPE)))
 k_rhs_central(const double* __restrict__ W, double* __restrict__ out, double* __restrict__ Rp,
               KGrid g, KGas gas, StepCoef sc, unsigned mask, int kc)
 {
-    __shared__ typename SmemOf<S, TX, TY, R, SPLIT>::type sm;
+    __shared__ typename SmemOf<Halo<SC, SV>::S, TX, TY, R, SPLIT>::type sm;
     const int k0 = blockIdx.z * kc;
     if constexpr (SPLIT)
-        march_split<S, TX, TY, R, UPD, PIMG>(sm, W, out, Rp, g, gas, sc, mask, blockIdx.x * TX,
-                                             blockIdx.y * TY, k0, min(k0 + kc, g.nz));
+        march_split<SC, SV, TX, TY, R, UPD, PIMG>(sm, W, out, Rp, g, gas, sc, mask, blockIdx.x * TX,
+                                                  blockIdx.y * TY, k0, min(k0 + kc, g.nz));
     else
-        march<S, TX, TY, R, UPD, PIMG>(sm, W, out, Rp, g, gas, sc, mask, blockIdx.x * TX,
-                                       blockIdx.y * TY, k0, min(k0 + kc, g.nz));
+        march<SC, SV, TX, TY, R, UPD, PIMG>(sm, W, out, Rp, g, gas, sc, mask, blockIdx.x * TX,
+                                            blockIdx.y * TY, k0, min(k0 + kc, g.nz));
 }
 
 // Persistent batched kernel: each workgroup pulls (box, column tile,
@@ -1167,10 +1191,10 @@ k_rhs_batch(const double* __restrict__ Wsrc, double* __restrict__ Wdst, double* 
         const TileDesc td = tiles[t];
         const BoxDesc& bd = boxes[td.box];
         if constexpr (SPLIT)
-            march_split<S, TX, TY, R, true, true>(sm, Wsrc + bd.woff, Wdst + bd.woff, Rp + bd.roff, bd.g,
+            march_split<S, S, TX, TY, R, true, true>(sm, Wsrc + bd.woff, Wdst + bd.woff, Rp + bd.roff, bd.g,
                                                   bd.gas, sc, (unsigned)SX_ALL, td.i0, td.j0, td.k0, td.k1);
         else
-            march<S, TX, TY, R, true, true>(sm, Wsrc + bd.woff, Wdst + bd.woff, Rp + bd.roff, bd.g,
+            march<S, S, TX, TY, R, true, true>(sm, Wsrc + bd.woff, Wdst + bd.woff, Rp + bd.roff, bd.g,
                                             bd.gas, sc, (unsigned)SX_ALL, td.i0, td.j0, td.k0, td.k1);
         __syncthreads();
     }
@@ -1218,11 +1242,12 @@ struct Tile {
     static constexpr int WPE = 2;
 };
 
-template <int S, typename R>
+template <int SC, int SV, typename R>
 static hipError_t launch_rhs_SR(const KGrid& g, const KGas& gas, const double* W, double* out,
                                 double* Rprev, const StepCoef* step, unsigned mask, bool pimg,
                                 hipStream_t st)
 {
+    constexpr int S = Halo<SC, SV>::S;
     constexpr int TX = Tile<R, S>::TX, TY = Tile<R, S>::TY, WPE = Tile<R, S>::WPE;
     constexpr bool SP = Tile<R, S>::SPLIT;
     constexpr int NTH = Tile<R, S>::NTH;
@@ -1251,17 +1276,36 @@ static hipError_t launch_rhs_SR(const KGrid& g, const KGas& gas, const double* W
     const int kc = (g.nz + nch - 1) / nch;
     dim3 grid((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY, (g.nz + kc - 1) / kc);
     if (step && pimg) {
-        hipLaunchKernelGGL((k_rhs_central<S, TX, TY, WPE, R, true, true, SP>), grid, dim3(NTH), 0, st,
-                           W, out, Rprev, g, gas, *step, (unsigned)SX_ALL, kc);
+        // periodic images are written only by the equal-order kernels (the
+        // handle never selects them for mixed orders)
+        if constexpr (SC == SV)
+            hipLaunchKernelGGL((k_rhs_central<SC, SV, TX, TY, WPE, R, true, true, SP>), grid, dim3(NTH), 0, st,
+                               W, out, Rprev, g, gas, *step, (unsigned)SX_ALL, kc);
+        else
+            return hipErrorInvalidValue;
     } else if (step) {
-        hipLaunchKernelGGL((k_rhs_central<S, TX, TY, WPE, R, true, false, SP>), grid, dim3(NTH), 0, st,
+        hipLaunchKernelGGL((k_rhs_central<SC, SV, TX, TY, WPE, R, true, false, SP>), grid, dim3(NTH), 0, st,
                            W, out, Rprev, g, gas, *step, (unsigned)SX_ALL, kc);
     } else {
         StepCoef none{0.0, 0.0, 0, 0};
-        hipLaunchKernelGGL((k_rhs_central<S, TX, TY, WPE, R, false, false, SP>), grid, dim3(NTH), 0,
+        hipLaunchKernelGGL((k_rhs_central<SC, SV, TX, TY, WPE, R, false, false, SP>), grid, dim3(NTH), 0,
                            st, W, out, Rprev, g, gas, none, mask, kc);
     }
     return hipGetLastError();
+}
+
+template <int SC, typename R>
+static hipError_t launch_rhs_CR(int Lv, const KGrid& g, const KGas& gas, const double* W, double* out,
+                                double* Rprev, const StepCoef* step, unsigned mask, bool pimg,
+                                hipStream_t st)
+{
+    switch (Lv) {
+    case 1: return launch_rhs_SR<SC, 1, R>(g, gas, W, out, Rprev, step, mask, pimg, st);
+    case 2: return launch_rhs_SR<SC, 2, R>(g, gas, W, out, Rprev, step, mask, pimg, st);
+    case 3: return launch_rhs_SR<SC, 3, R>(g, gas, W, out, Rprev, step, mask, pimg, st);
+    case 4: return launch_rhs_SR<SC, 4, R>(g, gas, W, out, Rprev, step, mask, pimg, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename R>
@@ -1270,10 +1314,10 @@ static hipError_t launch_rhs_R(const KGrid& g, const KGas& gas, const KScheme& s
                                bool pimg, hipStream_t st)
 {
     switch (sc.L) {
-    case 1: return launch_rhs_SR<1, R>(g, gas, W, out, Rprev, step, mask, pimg, st);
-    case 2: return launch_rhs_SR<2, R>(g, gas, W, out, Rprev, step, mask, pimg, st);
-    case 3: return launch_rhs_SR<3, R>(g, gas, W, out, Rprev, step, mask, pimg, st);
-    case 4: return launch_rhs_SR<4, R>(g, gas, W, out, Rprev, step, mask, pimg, st);
+    case 1: return launch_rhs_CR<1, R>(sc.Lv, g, gas, W, out, Rprev, step, mask, pimg, st);
+    case 2: return launch_rhs_CR<2, R>(sc.Lv, g, gas, W, out, Rprev, step, mask, pimg, st);
+    case 3: return launch_rhs_CR<3, R>(sc.Lv, g, gas, W, out, Rprev, step, mask, pimg, st);
+    case 4: return launch_rhs_CR<4, R>(sc.Lv, g, gas, W, out, Rprev, step, mask, pimg, st);
     default: return hipErrorInvalidValue;
     }
 }

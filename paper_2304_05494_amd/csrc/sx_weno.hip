@@ -255,11 +255,47 @@ __global__ void k_zero_counts(int* p)
     if (threadIdx.x < 4) p[threadIdx.x] = 0;
 }
 
+// Seventh-order WENO (Balsara-Shu) at i+1/2 from v[0 .. 6] = v_{i-3 .. i+3}.
+// Candidate k interpolates the cell averages of cells i-3+k .. i+k by a
+// cubic P in the cell index t (t = 0 at cell i); the reconstruction of cell
+// i's polynomial at its right face is v_i + P'(0)/2 + P''(0)/12, and the
+// Jiang-Shu indicator (the integral over the cell of the squared first to
+// third derivatives, scaled by powers of the width) is
+// P1^2 + 13/3 P2^2 + 781/20 P3^2 with P = sum_n P_n t^n -- a sum of squares,
+// which keeps it accurate on smooth data where it is tiny. P_n come from the
+// forward differences of the four values (Newton form about the first).
+// Linear weights (1, 12, 18, 4)/35.
+template <typename R>
+__device__ __forceinline__ R weno7_left(const R* v, R eps)
+{
+    R q[4], a[4];
+    const R dw[4] = {R(1.0 / 35.0), R(12.0 / 35.0), R(18.0 / 35.0), R(4.0 / 35.0)};
+    // P1 = d1 + c1 d2 + c2 d3, P2 = d2/2 + c3 d3, P3 = d3/6, for first node a = k-3
+    const R c1[4] = {R(2.5), R(1.5), R(0.5), R(-0.5)};
+    const R c2[4] = {R(11.0 / 6.0), R(1.0 / 3.0), R(-1.0 / 6.0), R(1.0 / 3.0)};
+    const R c3[4] = {R(1.0), R(0.5), R(0.0), R(-0.5)};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const R y0 = v[k], y1 = v[k + 1], y2 = v[k + 2], y3 = v[k + 3];
+        const R d1 = y1 - y0;
+        const R d2 = (y2 - y1) - d1;
+        const R d3 = ((y3 - y2) - (y2 - y1)) - d2;
+        const R P1 = d1 + c1[k] * d2 + c2[k] * d3;
+        const R P2 = R(0.5) * d2 + c3[k] * d3;
+        const R P3 = d3 * R(1.0 / 6.0);
+        q[k] = v[3] + R(0.5) * P1 + P2 * R(1.0 / 6.0);
+        const R b = P1 * P1 + R(13.0 / 3.0) * P2 * P2 + R(781.0 / 20.0) * P3 * P3;
+        a[k] = dw[k] / ((eps + b) * (eps + b));
+    }
+    return (a[0] * q[0] + a[1] * q[1] + a[2] * q[2] + a[3] * q[3]) / (a[0] + a[1] + a[2] + a[3]);
+}
+
 // Jiang-Shu WENO reconstruction at i+1/2 from v[0 .. 2r-2] = v_{i-r+1 .. i+r-1}
 template <int RW, typename R>
 __device__ __forceinline__ R weno_left(const R* v, R eps)
 {
     if (RW == 1) return v[0];
+    if (RW == 4) return weno7_left<R>(v, eps);
     if (RW == 2) {
         const R vm = v[0], v0 = v[1], vp = v[2];
         const R q0 = R(0.5) * (-vm + R(3) * v0), q1 = R(0.5) * (v0 + vp);
@@ -543,7 +579,8 @@ hipError_t launch_faces_L(int RW, const KGrid& g, const KGas& gas, double eps, u
     switch (RW) {
     case 1: return launch_faces<L, 1, R>(g, gas, eps, mask, W, b, st);
     case 2: return launch_faces<L, 2, R>(g, gas, eps, mask, W, b, st);
-    default: return launch_faces<L, 3, R>(g, gas, eps, mask, W, b, st);
+    case 3: return launch_faces<L, 3, R>(g, gas, eps, mask, W, b, st);
+    default: return launch_faces<L, 4, R>(g, gas, eps, mask, W, b, st);
     }
 }
 

@@ -43,6 +43,8 @@ def _run_oracle(case, Wn, dt, steps):
     Rp = np.zeros((5, case.nz, case.ny, case.nx))
     for s in range(steps):
         o.rk3_step(Wo, Rp, dt)
+        if (s + 1) % 5 == 0:
+            print(f"  oracle step {s + 1}/{steps}", flush=True)
     return o, Wo
 
 

@@ -57,20 +57,21 @@ def test_flag_fractions_match_oracle():
     np.testing.assert_allclose(np.array(d.weno_fraction), ref[12:15], rtol=0, atol=1e-12)
 
 
+@pytest.mark.parametrize("order", [5, 7])
 @pytest.mark.parametrize("base", ["tgv", "channel"])
-def test_weno_on_every_face(base):
+def test_weno_on_every_face(base, order):
     if base == "tgv":
-        case = inputs.tgv_case(24, mach=0.4, sensor=1, sensor_thr=-1.0)
+        case = inputs.tgv_case(24, mach=0.4, sensor=1, sensor_thr=-1.0, weno_order=order)
     else:
         case = inputs.Case(**{**inputs.channel_case(70, 36, 20).__dict__, "sensor": 1,
-                              "sensor_thr": -1.0})
+                              "sensor_thr": -1.0, "weno_order": order})
     Wn = np.ascontiguousarray(inputs.fields(case))
     h, got = _rhs(case, Wn)
     ref = oracle_for(case).rhs(Wn.copy())
     assert_rhs_close(got, ref, 1e-11)
 
 
-@pytest.mark.parametrize("order", [1, 3, 5])
+@pytest.mark.parametrize("order", [1, 3, 5, 7])
 def test_injected_random_flags(order):
     case = inputs.tgv_case(20, mach=0.3, sensor=1, weno_order=order)
     n = case.nx
@@ -144,3 +145,25 @@ def test_full_size_shock_boundary_layer_rhs_sampled_points():
     torch.cuda.empty_cache()
     ref = o.rhs_points(Wn, pts)
     assert_rhs_close(got.T[:, :, None, None], ref.T[:, :, None, None], 1e-11)
+
+
+def test_hybrid_weno7_shock_boundary_layer():
+    """Sensor-selected WENO-7 faces on the reduced shock/boundary-layer block
+    (four ghost layers), RHS and two RK3 steps against the oracle."""
+    case = inputs.Case(**{**SBL.__dict__, "weno_order": 7})
+    Wn = np.ascontiguousarray(inputs.fields(case))
+    o = oracle_for(case)
+    h, got = _rhs(case, Wn)
+    assert_rhs_close(got, o.rhs(Wn.copy()), 1e-11)
+    dt = o.compute_dt(Wn.copy(), case.cfl)
+    h2 = sx.Handle(case)
+    h2.sx_bind(h2.to_layout(Wn))
+    for _ in range(2):
+        h2.sx_rk3_step(dt)
+    torch.cuda.synchronize()
+    Wo = Wn.copy()
+    Rp = np.zeros((5, case.nz, case.ny, case.nx))
+    for _ in range(2):
+        o.rk3_step(Wo, Rp, dt)
+    err = rel_err_per_field(h2.interior(h2.state), o.interior(Wo))
+    assert np.all(err < 1e-12), err
