@@ -48,6 +48,7 @@ class _Params(ctypes.Structure):
         ("visc_order", ctypes.c_int),
         ("sensor", ctypes.c_int), ("sensor_thr", ctypes.c_double),
         ("sensor_eps", ctypes.c_double), ("weno_eps", ctypes.c_double),
+        ("central_flux", ctypes.c_int), ("keep_n", ctypes.c_int),
     ]
 
 
@@ -76,6 +77,8 @@ class Params:
     sensor_thr: float = 0.5
     sensor_eps: float = 1.0
     weno_eps: float = 1e-6
+    central_flux: int = 0      # 0 split form, 1 KEEP-n
+    keep_n: int = 0            # KEEP-n series terms beyond the first (< 0: exact log means)
 
     def c(self) -> _Params:
         p = _Params()

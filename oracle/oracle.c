@@ -8,7 +8,8 @@
  * What it computes follows Section 2 (Numerical Methods) of the paper:
  *  - compressible Navier-Stokes, ideal gas, Cartesian finite differences;
  *  - convective terms in the skew-symmetric split form written as face
- *    fluxes (Pirozzoli 2010, cited there), central order 2..8;
+ *    fluxes (Pirozzoli 2010, cited there), central order 2..8, or the
+ *    optional KEEP-n flux (Tamaki, Kuya and Kawai, cited there);
  *  - WENO reconstruction of characteristic fluxes, projected back on the
  *    right eigenvectors, on faces a modified Ducros sensor flags
  *    (STREAmS-1, cited there);
@@ -83,6 +84,7 @@ int orc_validate(const orc_params* p)
     if (p->central_order < 2 || p->central_order > 8 || p->central_order % 2) return 2;
     if (p->visc_order < 2 || p->visc_order > 8 || p->visc_order % 2) return 3;
     if (p->weno_order != 1 && p->weno_order != 3 && p->weno_order != 5 && p->weno_order != 7) return 4;
+    if (p->central_flux != 0 && p->central_flux != 1) return 7;
     for (d = 0; d < 3; ++d) {
         int n = d == 0 ? p->nx : (d == 1 ? p->ny : p->nz);
         if ((p->bc[2 * d] == ORC_BC_PERIODIC) != (p->bc[2 * d + 1] == ORC_BC_PERIODIC)) return 5;
@@ -465,6 +467,75 @@ static void central_flux_line(int L, const double* a, int d,
 }
 
 /* ------------------------------------------------------------------ */
+/* KEEP-n central flux (Section 2: the optional kinetic-energy and      */
+/* entropy preserving scheme of Tamaki, Kuya and Kawai). Reading: the    */
+/* two-point flux that conserves the entropy rho s / (gamma - 1), with   */
+/* s = ln p - gamma ln rho, and is kinetic-energy preserving (momentum   */
+/* flux = mass flux times the mean velocity plus the mean pressure):      */
+/*   F_rho = rho_ln  (ud_A + ud_B)/2                                       */
+/*   F_mom = F_rho   (u_A + u_B)/2 + (p_A + p_B)/2 e_d                     */
+/*   F_E   = F_rho ( 1 / ((gamma-1) b_ln) + (u_A.u_B)/2 )                  */
+/*           + (p_A ud_B + p_B ud_A)/2,            b = rho / p,            */
+/* where x_ln = (x_B - x_A)/(ln x_B - ln x_A) is the logarithmic mean. The */
+/* "n" of KEEP-n: 1/x_ln = 2/(x_A+x_B) * sum_m xi^(2m)/(2m+1), xi =        */
+/* (x_B-x_A)/(x_B+x_A), cut after the terms m = 0..n (n < 0: the exact     */
+/* mean). Used in the same high-order form as the split flux:              */
+/*   F_{i+1/2} = sum_l 2 a_l sum_{m<l} F(node n - m s, node n + (l-m) s).   */
+/* ------------------------------------------------------------------ */
+static double inv_log_mean(double xa, double xb, int nterms)
+{
+    double sum = xa + xb, xi = (xb - xa) / sum, x2 = xi * xi, t = 1.0, S = 0.0;
+    int m;
+    if (nterms < 0) {
+        if (fabs(xi) >= 0.1) return (log(xb) - log(xa)) / (xb - xa);
+        nterms = 16;   /* xi^34/35 < 1e-35: exact to rounding */
+    }
+    for (m = 0; m <= nterms; ++m) {
+        S += t / (2.0 * m + 1.0);
+        t *= x2;
+    }
+    return 2.0 / sum * S;
+}
+
+static void keep_pair_flux(const orc_params* p, int d, const double* qa, const double* qb,
+                           double F[NV])
+{
+    double uda = qa[Q_U + d], udb = qb[Q_U + d];
+    double frho = 0.5 * (uda + udb) / inv_log_mean(qa[Q_RHO], qb[Q_RHO], p->keep_n);
+    double ba = qa[Q_RHO] / qa[Q_P], bb = qb[Q_RHO] / qb[Q_P];
+    double uu = qa[Q_U] * qb[Q_U] + qa[Q_V] * qb[Q_V] + qa[Q_W] * qb[Q_W];
+    double K = inv_log_mean(ba, bb, p->keep_n) / (p->gamma - 1.0) + 0.5 * uu;
+    F[0] = frho;
+    F[1] = frho * 0.5 * (qa[Q_U] + qb[Q_U]);
+    F[2] = frho * 0.5 * (qa[Q_V] + qb[Q_V]);
+    F[3] = frho * 0.5 * (qa[Q_W] + qb[Q_W]);
+    F[1 + d] += 0.5 * (qa[Q_P] + qb[Q_P]);
+    F[4] = frho * K + 0.5 * (qa[Q_P] * udb + qb[Q_P] * uda);
+}
+
+/* KEEP-n face flux between node n and node n+s (primitive field Q with  */
+/* variable stride nvol).                                                */
+static void keep_flux_line(const orc_params* p, int L, const double* a, int d, const double* Q,
+                           long nvol, long n, long s, double F[NV])
+{
+    int l, m, q, v;
+    for (q = 0; q < NV; ++q) F[q] = 0.0;
+    for (l = 1; l <= L; ++l) {
+        double cl = 2.0 * a[l];
+        for (m = 0; m < l; ++m) {
+            long A = n - m * s, B = n + (l - m) * s;
+            double qa[NQ], qb[NQ], f[NV];
+            for (v = 0; v < NQ; ++v) {
+                qa[v] = Q[v * nvol + A];
+                qb[v] = Q[v * nvol + B];
+            }
+            keep_pair_flux(p, d, qa, qb, f);
+            for (q = 0; q < NV; ++q) F[q] += cl * f[q];
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
 /* WENO characteristic flux (Section 2): characteristic fluxes are      */
 /* reconstructed with WENO and projected back on the right eigenvectors */
 /* of the Euler equations. Textbook pieces used:                        */
@@ -688,7 +759,9 @@ static void face_flux(const ctx* c, const double* W, int d, long n, int use_weno
 {
     const double* Q = c->Q;
     long s = c->sxyz[d];
-    if (!use_weno) {
+    if (!use_weno && c->p->central_flux == 1) {
+        keep_flux_line(c->p, c->L, c->a, d, Q, c->nvol, n, s, F);
+    } else if (!use_weno) {
         central_flux_line(c->L, c->a, d, Q + Q_RHO * c->nvol, Q + Q_U * c->nvol,
                           Q + Q_V * c->nvol, Q + Q_W * c->nvol, Q + Q_P * c->nvol,
                           Q + Q_H * c->nvol, n, s, F);

@@ -37,6 +37,9 @@ typedef struct {
     int visc_order;         /* 2,4,6,8 */
     int sensor;             /* 0 off, 1 Ducros */
     double sensor_thr, sensor_eps, weno_eps;
+    int central_flux;       /* 0 split form (Pirozzoli), 1 KEEP-n */
+    int keep_n;             /* KEEP-n: terms of the log-mean series beyond
+                               the first; < 0 = exact logarithmic means */
 } orc_params;
 
 int    orc_validate(const orc_params* p);

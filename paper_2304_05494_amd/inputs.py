@@ -51,6 +51,8 @@ class Case:
     sensor_thr: float = 0.5
     sensor_eps: float = 1.0
     weno_eps: float = 1e-6
+    central_flux: int = 0          # 0 split form (Pirozzoli), 1 KEEP-n
+    keep_n: int = 0                # KEEP-n: log-mean series terms beyond the first
     cfl: float = 0.5
     steps: int = 10
     seed: int | None = None
