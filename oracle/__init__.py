@@ -49,6 +49,7 @@ class _Params(ctypes.Structure):
         ("sensor", ctypes.c_int), ("sensor_thr", ctypes.c_double),
         ("sensor_eps", ctypes.c_double), ("weno_eps", ctypes.c_double),
         ("central_flux", ctypes.c_int), ("keep_n", ctypes.c_int),
+        ("bulk_forcing", ctypes.c_int),
     ]
 
 
@@ -79,6 +80,7 @@ class Params:
     weno_eps: float = 1e-6
     central_flux: int = 0      # 0 split form, 1 KEEP-n
     keep_n: int = 0            # KEEP-n series terms beyond the first (< 0: exact log means)
+    bulk_forcing: int = 0      # 1: uniform streamwise force holding the bulk momentum
 
     def c(self) -> _Params:
         p = _Params()

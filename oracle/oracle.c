@@ -14,6 +14,8 @@
  *    right eigenvectors, on faces a modified Ducros sensor flags
  *    (STREAmS-1, cited there);
  *  - viscous terms expanded in Laplacian form, central FD order 2..8;
+ *  - optionally, the channel's bulk forcing (a uniform streamwise force
+ *    holding the mass flow);
  *  - third-order low-storage Runge-Kutta in time.
  * The paper states these only in words; every concrete formula below is the
  * published method it names or, where the paper is silent, the reading
@@ -944,6 +946,44 @@ static void prepare(ctx* c, double* W, flagset* fs, unsigned char** own,
     }
 }
 
+static double pairwise(const double* x, long n);
+
+/* ------------------------------------------------------------------ */
+/* Bulk forcing of the channel (the paper's force_rhs_1, a sum          */
+/* reduction, Table 2). Reading: a spatially uniform streamwise body    */
+/* force f, set at every evaluation of the full right-hand side so that */
+/* the volume integral of the x-momentum right-hand side vanishes (the  */
+/* bulk momentum, hence the mass flow, stays fixed):                     */
+/*   f = - sum V R_rhou / sum V,  R_rhou += f,  R_rhoE += f u,           */
+/* with the force's work f u at every node and V = dx y_eta dz.           */
+/* ------------------------------------------------------------------ */
+static void bulk_force(const ctx* c, double* R)
+{
+    const orc_params* p = c->p;
+    long nint = (long)p->nx * p->ny * p->nz, m;
+    double* t = (double*)malloc(sizeof(double) * nint);
+    double* vol = (double*)malloc(sizeof(double) * nint);
+    double f;
+    int i, j, k;
+    for (k = 0; k < p->nz; ++k)
+        for (j = 0; j < p->ny; ++j)
+            for (i = 0; i < p->nx; ++i) {
+                m = ((long)k * p->ny + j) * p->nx + i;
+                vol[m] = c->dx * c->y_eta[j] * c->dz;
+                t[m] = vol[m] * R[1 * nint + m];
+            }
+    f = -pairwise(t, nint) / pairwise(vol, nint);
+    for (k = 0; k < p->nz; ++k)
+        for (j = 0; j < p->ny; ++j)
+            for (i = 0; i < p->nx; ++i) {
+                m = ((long)k * p->ny + j) * p->nx + i;
+                R[1 * nint + m] += f;
+                R[4 * nint + m] += f * c->Q[Q_U * c->nvol + vidx(c, i, j, k)];
+            }
+    free(t);
+    free(vol);
+}
+
 void orc_rhs(const orc_params* p, double* W, double* R, unsigned mask,
              const unsigned char* fx, const unsigned char* fy, const unsigned char* fz)
 {
@@ -964,6 +1004,7 @@ void orc_rhs(const orc_params* p, double* W, double* R, unsigned mask,
                 for (v = 0; v < NV; ++v) R[v * nint + ((long)k * p->ny + j) * p->nx + i] = Rp[v];
             }
     }
+    if (p->bulk_forcing && mask == ORC_ALL) bulk_force(&c, R);
     free(own[0]); free(own[1]); free(own[2]);
     ctx_free(&c);
 }

@@ -40,6 +40,8 @@ typedef struct {
     int central_flux;       /* 0 split form (Pirozzoli), 1 KEEP-n */
     int keep_n;             /* KEEP-n: terms of the log-mean series beyond
                                the first; < 0 = exact logarithmic means */
+    int bulk_forcing;       /* 1: uniform streamwise body force holding the
+                               bulk x-momentum fixed (full right-hand side) */
 } orc_params;
 
 int    orc_validate(const orc_params* p);

@@ -53,6 +53,7 @@ class Case:
     weno_eps: float = 1e-6
     central_flux: int = 0          # 0 split form (Pirozzoli), 1 KEEP-n
     keep_n: int = 0                # KEEP-n: log-mean series terms beyond the first
+    bulk_forcing: int = 0          # 1: uniform streamwise force holding the bulk momentum
     cfl: float = 0.5
     steps: int = 10
     seed: int | None = None
