@@ -50,6 +50,7 @@ class _Params(ctypes.Structure):
         ("sensor_eps", ctypes.c_double), ("weno_eps", ctypes.c_double),
         ("central_flux", ctypes.c_int), ("keep_n", ctypes.c_int),
         ("bulk_forcing", ctypes.c_int),
+        ("thermo", ctypes.c_int), ("nasa", ctypes.c_double * 5), ("t_ref", ctypes.c_double),
     ]
 
 
@@ -81,12 +82,17 @@ class Params:
     central_flux: int = 0      # 0 split form, 1 KEEP-n
     keep_n: int = 0            # KEEP-n series terms beyond the first (< 0: exact log means)
     bulk_forcing: int = 0      # 1: uniform streamwise force holding the bulk momentum
+    thermo: int = 0            # 1: thermally perfect gas, c_p/R = sum_k nasa[k] (T t_ref)^k
+    nasa: tuple = (3.5, 0.0, 0.0, 0.0, 0.0)
+    t_ref: float = 300.0       # kelvin at T = 1
 
     def c(self) -> _Params:
         p = _Params()
         for name, _ in _Params._fields_:
             if name == "bc":
                 p.bc[:] = list(self.bc)
+            elif name == "nasa":
+                p.nasa[:] = [float(x) for x in self.nasa]
             else:
                 setattr(p, name, getattr(self, name))
         return p
@@ -121,6 +127,9 @@ def lib():
         L.orc_diagnostics.argtypes = [P, dp, dp, dp]
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_set_num_threads.argtypes = [ctypes.c_int]
+        L.orc_thermo_eval.argtypes = [P, ctypes.c_double, dp]
+        L.orc_thermo_T.argtypes = [P, ctypes.c_double]
+        L.orc_thermo_T.restype = ctypes.c_double
         L.orc_fd_coeffs.argtypes = [ctypes.c_int, dp, dp]
         L.orc_weno_left.argtypes = [ctypes.c_int, ctypes.c_double, dp]
         L.orc_weno_left.restype = ctypes.c_double
@@ -233,6 +242,15 @@ class Oracle:
 
     def compute_dt(self, W: np.ndarray, cfl: float) -> float:
         return lib().orc_compute_dt(ctypes.byref(self._c), _dp(W), cfl)
+
+    def thermo_eval(self, T: float):
+        """(c_p, c_v, e, dc_p/dT) of the gas at temperature T."""
+        out = np.zeros(4)
+        lib().orc_thermo_eval(ctypes.byref(self._c), float(T), _dp(out))
+        return out
+
+    def thermo_T(self, e: float) -> float:
+        return lib().orc_thermo_T(ctypes.byref(self._c), float(e))
 
     def diagnostics(self, W: np.ndarray, R: np.ndarray | None = None) -> np.ndarray:
         out = np.zeros(NDIAG)

@@ -87,6 +87,9 @@ int orc_validate(const orc_params* p)
     if (p->visc_order < 2 || p->visc_order > 8 || p->visc_order % 2) return 3;
     if (p->weno_order != 1 && p->weno_order != 3 && p->weno_order != 5 && p->weno_order != 7) return 4;
     if (p->central_flux != 0 && p->central_flux != 1) return 7;
+    /* the thermally perfect gas is read for the central path (the WENO     */
+    /* eigenvectors and the KEEP-n entropy flux assume a constant gamma)     */
+    if (p->thermo && (p->sensor || p->central_flux)) return 8;
     for (d = 0; d < 3; ++d) {
         int n = d == 0 ? p->nx : (d == 1 ? p->ny : p->nz);
         if ((p->bc[2 * d] == ORC_BC_PERIODIC) != (p->bc[2 * d + 1] == ORC_BC_PERIODIC)) return 5;
@@ -219,17 +222,77 @@ static void ctx_free(ctx* c)
 /*   H = (rhoE + p) / rho,  c^2 = gamma p / rho = T / M^2,              */
 /*   mu = T^s / Re,  k = mu / ((gamma-1) M^2 Pr).                       */
 /* ------------------------------------------------------------------ */
+/* ------------------------------------------------------------------ */
+/* Thermally perfect gas (Section 2, last paragraph: specific heats      */
+/* depending on temperature through NASA polynomials, McBride et al.).  */
+/* Reading: one 7-coefficient NASA range, c_p / R_g = sum_k a_k theta^k, */
+/* k = 0..4, theta = T t_ref the dimensional temperature; the gas stays */
+/* thermally ideal, p = rho R_g T with R_g = 1/(gamma M^2) (gamma, M of  */
+/* the reference state). Per unit mass, nondimensional:                  */
+/*   c_p(T) = R_g P(T),  c_v = c_p - R_g,                                */
+/*   e(T) = int_0^T c_v = R_g [(a_0 - 1) T + sum_{k>=1} a_k t_ref^k       */
+/*          T^(k+1) / (k+1)],                                              */
+/* and T from e by Newton's method on e(T) - e = 0. With a_0 = gamma /    */
+/* (gamma - 1) and a_k = 0 otherwise this is the calorically perfect gas. */
+/* The heat conductivity is k = mu c_p(T) / Pr.                           */
+/* ------------------------------------------------------------------ */
+static double rgas(const orc_params* p) { return 1.0 / (p->gamma * p->mach * p->mach); }
+
+void orc_thermo_eval(const orc_params* p, double T, double* out)
+{
+    double R = rgas(p), th = T * p->t_ref, P = 0.0, dP = 0.0, E = 0.0, tk = 1.0;
+    int k;
+    for (k = 0; k <= 4; ++k) {
+        P += p->nasa[k] * tk;                                  /* theta^k */
+        if (k >= 1) dP += k * p->nasa[k] * tk / th * p->t_ref; /* dP/dT */
+        tk *= th;
+    }
+    /* e = R [ (a0-1) T + sum_{k>=1} a_k t_ref^k T^(k+1)/(k+1) ] */
+    tk = T;
+    for (k = 0; k <= 4; ++k) {
+        double a = k == 0 ? p->nasa[0] - 1.0 : p->nasa[k];
+        E += a * tk / (k + 1);
+        tk *= th;
+    }
+    out[0] = R * P;
+    out[1] = R * (P - 1.0);
+    out[2] = R * E;
+    out[3] = R * dP;
+}
+
+double orc_thermo_T(const orc_params* p, double e)
+{
+    double f[4], T, dT;
+    int it;
+    orc_thermo_eval(p, 1.0, f);
+    T = e / f[1];
+    for (it = 0; it < 100; ++it) {
+        orc_thermo_eval(p, T, f);
+        dT = (f[2] - e) / f[1];
+        T -= dT;
+        if (fabs(dT) <= 1e-15 * fabs(T)) break;
+    }
+    return T;
+}
+
 static void cons_to_prim(const orc_params* p, const double w[NV], double q[NQ])
 {
     double rho = w[0];
     double u = w[1] / rho, v = w[2] / rho, ww = w[3] / rho;
-    double pr = (p->gamma - 1.0) * (w[4] - 0.5 * rho * (u * u + v * v + ww * ww));
+    double pr, T;
+    if (p->thermo) {
+        T = orc_thermo_T(p, w[4] / rho - 0.5 * (u * u + v * v + ww * ww));
+        pr = rho * T * rgas(p);
+    } else {
+        pr = (p->gamma - 1.0) * (w[4] - 0.5 * rho * (u * u + v * v + ww * ww));
+        T = p->gamma * p->mach * p->mach * pr / rho;
+    }
     q[Q_RHO] = rho;
     q[Q_U] = u;
     q[Q_V] = v;
     q[Q_W] = ww;
     q[Q_P] = pr;
-    q[Q_T] = p->gamma * p->mach * p->mach * pr / rho;
+    q[Q_T] = T;
     q[Q_H] = (w[4] + pr) / rho;
 }
 
@@ -240,7 +303,23 @@ static void prim_to_cons(const orc_params* p, double rho, double u, double v,
     out[1] = rho * u;
     out[2] = rho * v;
     out[3] = rho * w;
-    out[4] = pr / (p->gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w);
+    if (p->thermo) {
+        double f[4];
+        orc_thermo_eval(p, pr / (rho * rgas(p)), f);
+        out[4] = rho * f[2] + 0.5 * rho * (u * u + v * v + w * w);
+    } else {
+        out[4] = pr / (p->gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w);
+    }
+}
+
+/* Ratio of specific heats at a node (gamma, or c_p/c_v of the thermally */
+/* perfect gas).                                                         */
+static double gamma_at(const orc_params* p, double T)
+{
+    double f[4];
+    if (!p->thermo) return p->gamma;
+    orc_thermo_eval(p, T, f);
+    return f[0] / f[1];
 }
 
 void orc_primitives(const orc_params* p, const double* W, double* Q)
@@ -843,7 +922,13 @@ static void viscous_point(const ctx* c, long n, int j, double Vout[NV])
     int a, b;
     double Tc = T[n];
     double mu = pow(Tc, p->visc_exp) / p->reynolds;
-    double kc = mu * c->cp / p->prandtl;
+    double kc = mu * c->cp / p->prandtl, kT = 0.0;   /* kT = (dk/dT) / k beyond s/T */
+    if (p->thermo) {
+        double f[4];
+        orc_thermo_eval(p, Tc, f);
+        kc = mu * f[0] / p->prandtl;
+        kT = f[3] / f[0];
+    }
     double dmu[3], dk[3];
     for (a = 0; a < 3; ++a) {          /* g[a][b] = d_b u_a */
         for (b = 0; b < 3; ++b) g[a][b] = d1v(c, u[a], n, b, j);
@@ -860,7 +945,7 @@ static void viscous_point(const ctx* c, long n, int j, double Vout[NV])
         for (b = 0; b < 3; ++b)
             if (b != a) dth[a] += dmixed(c, u[b], n, a, b, j);
         dmu[a] = p->visc_exp * mu / Tc * gT[a];
-        dk[a] = p->visc_exp * kc / Tc * gT[a];
+        dk[a] = (p->visc_exp * kc / Tc + kc * kT) * gT[a];
     }
     double VE = 0.0;
     for (a = 0; a < 3; ++a) {
@@ -1084,13 +1169,14 @@ double orc_compute_dt(const orc_params* p, double* W, double cfl)
             for (i = 0; i < p->nx; ++i) {
                 long n = vidx(&c, i, j, k);
                 double rho = c.Q[Q_RHO * c.nvol + n];
-                double cs = sqrt(p->gamma * c.Q[Q_P * c.nvol + n] / rho);
+                double gm = gamma_at(p, c.Q[Q_T * c.nvol + n]);
+                double cs = sqrt(gm * c.Q[Q_P * c.nvol + n] / rho);
                 double mu = pow(c.Q[Q_T * c.nvol + n], p->visc_exp) / p->reynolds;
                 double hy = c.y_eta[j];
                 double conv = (fabs(c.Q[Q_U * c.nvol + n]) + cs) / c.dx +
                               (fabs(c.Q[Q_V * c.nvol + n]) + cs) / hy +
                               (fabs(c.Q[Q_W * c.nvol + n]) + cs) / c.dz;
-                double visc = 2.0 * p->gamma * mu / (rho * p->prandtl) *
+                double visc = 2.0 * gm * mu / (rho * p->prandtl) *
                               (1.0 / (c.dx * c.dx) + 1.0 / (hy * hy) + 1.0 / (c.dz * c.dz));
                 if (conv + visc > gmax) gmax = conv + visc;
             }
@@ -1163,7 +1249,8 @@ void orc_diagnostics(const orc_params* p, double* W, const double* R, double* ou
                 if (pr < pmin) pmin = pr;
                 if (rho > 0.0 && pr > 0.0) {
                     double u = c.Q[Q_U * c.nvol + n], vv = c.Q[Q_V * c.nvol + n], w = c.Q[Q_W * c.nvol + n];
-                    double ma = sqrt((u * u + vv * vv + w * w) * rho / (p->gamma * pr));
+                    double ma = sqrt((u * u + vv * vv + w * w) * rho /
+                                     (gamma_at(p, c.Q[Q_T * c.nvol + n]) * pr));
                     if (ma > mach) mach = ma;
                 }
             }

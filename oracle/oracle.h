@@ -42,7 +42,17 @@ typedef struct {
                                the first; < 0 = exact logarithmic means */
     int bulk_forcing;       /* 1: uniform streamwise body force holding the
                                bulk x-momentum fixed (full right-hand side) */
+    int thermo;             /* 0 calorically perfect, 1 thermally perfect:
+                               c_p / R = sum_k nasa[k] (T t_ref)^k, k = 0..4 */
+    double nasa[5];         /* NASA polynomial coefficients a1..a5 (kelvin) */
+    double t_ref;           /* reference temperature in kelvin (T = 1) */
 } orc_params;
+
+/* Thermally perfect gas at nondimensional temperature T: out = (c_p, c_v,
+ * e, dc_p/dT) per unit mass, nondimensional (gas constant 1/(gamma M^2)). */
+void   orc_thermo_eval(const orc_params* p, double T, double* out);
+/* Temperature of specific internal energy e (Newton on e(T)). */
+double orc_thermo_T(const orc_params* p, double e);
 
 int    orc_validate(const orc_params* p);
 int    orc_ng(const orc_params* p);

@@ -54,6 +54,9 @@ class Case:
     central_flux: int = 0          # 0 split form (Pirozzoli), 1 KEEP-n
     keep_n: int = 0                # KEEP-n: log-mean series terms beyond the first
     bulk_forcing: int = 0          # 1: uniform streamwise force holding the bulk momentum
+    thermo: int = 0                # 1: thermally perfect gas (NASA polynomial c_p(T))
+    nasa: tuple = (3.5, 0.0, 0.0, 0.0, 0.0)   # c_p/R = sum_k nasa[k] (T t_ref)^k
+    t_ref: float = 300.0           # kelvin at nondimensional T = 1
     cfl: float = 0.5
     steps: int = 10
     seed: int | None = None
