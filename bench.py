@@ -56,6 +56,10 @@ def parse():
     ap.add_argument("--sweep", action="store_true",
                     help="add the stencil-order sweep (channel, C2..C8, FP64 and FP32-flux) and "
                          "the WENO-activation sweep (shock/boundary-layer block, injected flags)")
+    ap.add_argument("--sweep-f2", action="store_true",
+                    help="add the viscous-order (C6 V2..V8), WENO-order (W1..W7 on every face), "
+                         "thread-masking (the four grids of the paper's masking study) and "
+                         "grid-size (0.25 M to 134 M points) sweeps")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON autotune cache of the batched form (default: tune afresh)")
     return ap.parse_args()
@@ -260,6 +264,106 @@ def bench_order_sweep(args, Wn, dt):
             del h
             torch.cuda.empty_cache()
         out[f"C{order}V{order}"] = row
+    return out
+
+
+def bench_visc_order_sweep(args, Wn, dt):
+    """The channel block with sixth-order convection and viscous orders 2, 4,
+    6, 8 (the paper varies V2..V8 apart from C2..C8), FP64."""
+    import numpy as np
+    import torch
+    from paper_2304_05494_amd import inputs, sx
+    out = {}
+    for vo in (2, 4, 6, 8):
+        case = inputs.channel_case(central_order=6, visc_order=vo)
+        Wo = Wn if case.ng == inputs.channel_case().ng else np.ascontiguousarray(inputs.fields(case))
+        h = sx.Handle(case)
+        h.sx_bind(h.to_layout(Wo))
+        ms, kms = time_steps(h, dt, args.steps, args.warmup)
+        d = h.sx_diagnostics()
+        out[f"C6V{vo}"] = {"ms_per_step": ms, "launch_ms": kms,
+                           "roofline_frac": ALG_BYTES_PER_POINT_STEP / SUBSTEPS * case.points
+                           / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, "state_ok": d.status == sx.SX_OK}
+        del h
+        torch.cuda.empty_cache()
+    return out
+
+
+def bench_weno_order_sweep(args):
+    """WENO orders 1, 3, 5, 7 on every face of the channel block (sensor
+    threshold below zero), C6 + V6, FP64: RK3 step time against the order
+    (the paper's W1..W7 study)."""
+    import numpy as np
+    import torch
+    from paper_2304_05494_amd import inputs, sx
+    out = {}
+    dt = None
+    for wo in (1, 3, 5, 7):
+        case = inputs.channel_case(sensor=1, sensor_thr=-1.0, weno_order=wo)
+        Wo = np.ascontiguousarray(inputs.fields(case))
+        h = sx.Handle(case)
+        h.sx_bind(h.to_layout(Wo))
+        if dt is None:
+            dt = h.sx_compute_dt(case.cfl)
+        ms, kms = time_steps(h, dt, max(3, args.steps // 4), args.warmup)
+        d = h.sx_diagnostics()
+        out[f"W{wo}"] = {"ms_per_step": ms, "central_kernel_ms": kms,
+                         "weno_face_fraction": list(d.weno_fraction), "state_ok": d.status == sx.SX_OK}
+        del h, Wo
+        torch.cuda.empty_cache()
+    return out
+
+
+MASKING_GRIDS = ((384, 256, 384), (384, 256, 350), (420, 256, 350), (420, 250, 320))
+
+
+def bench_thread_masking(args):
+    """The paper's thread-masking grids (multiples of 128 in three, two, one
+    and no direction), channel-like flow, FP64: grind time (ms per RK3 step
+    per 1e8 points) for the central scheme and with WENO-5 on every face."""
+    import numpy as np
+    import torch
+    from paper_2304_05494_amd import inputs, sx
+    out = {}
+    for n, (nx, ny, nz) in enumerate(MASKING_GRIDS, 1):
+        row = {"grid": [nx, ny, nz]}
+        for name, kw in (("central", {}), ("weno", {"sensor": 1, "sensor_thr": -1.0})):
+            case = inputs.channel_case(nx, ny, nz, **kw)
+            Wo = np.ascontiguousarray(inputs.fields(case))
+            h = sx.Handle(case)
+            h.sx_bind(h.to_layout(Wo))
+            dt = h.sx_compute_dt(case.cfl)
+            steps = args.steps if name == "central" else max(3, args.steps // 4)
+            ms, kms = time_steps(h, dt, steps, args.warmup)
+            row[name] = {"ms_per_step": ms, "grind_ms_per_1e8_points": ms * 1e8 / case.points,
+                         "fused_kernel_ms": kms}
+            del h, Wo
+            torch.cuda.empty_cache()
+        out[f"grid{n}"] = row
+    return out
+
+
+def bench_grid_size_sweep(args):
+    """Grind time against the number of points (the paper's grid-size study):
+    channel-like blocks from 0.25 M to 134 M points, doubling, FP64 central."""
+    import numpy as np
+    import torch
+    from paper_2304_05494_amd import inputs, sx
+    out = {}
+    shapes = [(64, 64, 64), (128, 64, 64), (128, 128, 64), (128, 128, 128), (256, 128, 128),
+              (256, 256, 128), (256, 256, 256), (512, 256, 256), (512, 512, 256), (512, 512, 512)]
+    for nx, ny, nz in shapes:
+        case = inputs.channel_case(nx, ny, nz)
+        Wo = np.ascontiguousarray(inputs.fields(case))
+        h = sx.Handle(case)
+        h.sx_bind(h.to_layout(Wo))
+        dt = h.sx_compute_dt(case.cfl)
+        ms, kms = time_steps(h, dt, args.steps, args.warmup)
+        out[f"{nx}x{ny}x{nz}"] = {"points": case.points, "ms_per_step": ms,
+                                  "grind_ms_per_1e8_points": ms * 1e8 / case.points,
+                                  "fused_kernel_ms": kms}
+        del h, Wo
+        torch.cuda.empty_cache()
     return out
 
 
@@ -501,6 +605,11 @@ def main():
         line["tgv32"] = bench_tgv(args)
         line["shock_bl"] = bench_shock_bl(args)
         line["fp32_flux"]["error_vs_fp64_after_100_steps"] = fp32_error(case, Wn, dt, 100)
+    if args.sweep_f2:
+        line["visc_order_sweep"] = bench_visc_order_sweep(args, Wn, dt)
+        line["weno_order_sweep"] = bench_weno_order_sweep(args)
+        line["thread_masking"] = bench_thread_masking(args)
+        line["grid_size_sweep"] = bench_grid_size_sweep(args)
     if args.sweep:
         line["order_sweep"] = bench_order_sweep(args, Wn, dt)
         line["weno_activation_sweep"] = bench_activation_sweep(args)

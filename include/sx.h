@@ -71,6 +71,14 @@ enum { SX_CONV_X = 1, SX_CONV_Y = 2, SX_CONV_Z = 4, SX_VISC = 8, SX_ALL = 15 };
 /* precision of the flux arithmetic (state and RK registers are FP64). */
 enum { SX_FP64 = 0, SX_FP32_FLUX = 1 };
 
+/* Central convective flux (Section 2): the skew-symmetric split form, or the
+ * optional KEEP-n flux (kinetic-energy and entropy preserving: the
+ * entropy-conserving two-point flux with logarithmic means of density and of
+ * rho/p, each mean's series cut after keep_n terms). KEEP-n is built for the
+ * FP64 path of single blocks with the sensor off and equal convective and
+ * viscous orders; other combinations return SX_EUNSUPPORTED. */
+enum { SX_FLUX_SPLIT = 0, SX_FLUX_KEEP = 1 };
+
 typedef struct {
     int nx, ny, nz;           /* interior nodes */
     double lx, ly, lz;        /* domain lengths (x, z uniform: dx = lx/nx) */
@@ -87,6 +95,17 @@ typedef struct {
     double prandtl;
     double visc_exp;          /* mu = T^visc_exp / Re */
     double t_wall;            /* isothermal wall temperature */
+    int thermo;               /* 0 calorically perfect; 1 thermally perfect
+                                 (Section 2: specific heats from a NASA
+                                 polynomial): c_p / R = sum_k nasa[k] theta^k,
+                                 k = 0..4, theta = T t_ref in kelvin, R the gas
+                                 constant 1/(gamma mach^2) of the reference state;
+                                 e(T) = int_0^T c_v, T from e by Newton's method,
+                                 heat conductivity mu c_p(T) / Pr. Single blocks,
+                                 central split form, sensor off, equal orders;
+                                 otherwise SX_EUNSUPPORTED */
+    double nasa[5];           /* polynomial coefficients a1..a5 (per kelvin^k) */
+    double t_ref;             /* kelvin at T = 1 */
 } sx_gas;
 
 typedef struct {
@@ -102,6 +121,15 @@ typedef struct {
     double sensor_eps;        /* epsilon of the sensor denominator */
     double weno_eps;          /* epsilon of the WENO weights */
     int precision;            /* SX_FP64 or SX_FP32_FLUX */
+    int central_flux;         /* SX_FLUX_SPLIT (default) or SX_FLUX_KEEP */
+    int keep_n;               /* KEEP-n: terms of the logarithmic-mean series
+                                 beyond the first (0..16); < 0 = exact means */
+    int bulk_forcing;         /* 1: channel bulk forcing (the paper's force_rhs_1,
+                                 Table 2): a uniform streamwise body force set at
+                                 every full right-hand side so that the volume
+                                 integral of d(rho u)/dt vanishes, its work f u
+                                 added to the energy. Single blocks, sensor off;
+                                 sx_rhs applies it only with term_mask SX_ALL. */
 } sx_scheme;
 
 typedef struct {

@@ -102,8 +102,13 @@ int sx_validate(const sx_grid& g, const sx_gas& gas, const sx_scheme& s, int* ng
     if (s.weno_order != 1 && s.weno_order != 3 && s.weno_order != 5 && s.weno_order != 7) return SX_EINVAL;
     if (s.sensor != 0 && s.sensor != 1) return SX_EINVAL;
     if (s.precision != SX_FP64 && s.precision != SX_FP32_FLUX) return SX_EINVAL;
+    if (s.central_flux != SX_FLUX_SPLIT && s.central_flux != SX_FLUX_KEEP) return SX_EINVAL;
+    if (s.central_flux == SX_FLUX_KEEP && s.keep_n > 16) return SX_EINVAL;
+    if (s.bulk_forcing != 0 && s.bulk_forcing != 1) return SX_EINVAL;
     if (!(gas.gamma > 1.0) || !(gas.mach > 0.0) || !(gas.reynolds > 0.0) || !(gas.prandtl > 0.0))
         return SX_EINVAL;
+    if (gas.thermo != 0 && gas.thermo != 1) return SX_EINVAL;
+    if (gas.thermo && !(gas.t_ref > 0.0)) return SX_EINVAL;
     if (!(g.lx > 0.0) || !(g.ly > 0.0) || !(g.lz > 0.0)) return SX_EINVAL;
 
     if (g.ymap < SX_Y_UNIFORM || g.ymap > SX_Y_TANH1) return SX_EINVAL;
@@ -124,6 +129,17 @@ int sx_validate(const sx_grid& g, const sx_gas& gas, const sx_scheme& s, int* ng
     const long long var_bytes = 8 * px * (g.ny + 2LL * ng) * (g.nz + 2LL * ng);
     const long long int_bytes = 8LL * g.nx * g.ny * g.nz;
     if (var_bytes >= (1LL << 32) || int_bytes >= (1LL << 32)) return SX_EINVAL;
+    // thermally perfect gas: central split-form path with one order for
+    // convective and viscous terms (WENO eigenvectors and the KEEP-n entropy
+    // flux assume a constant gamma)
+    if (gas.thermo && (s.sensor || s.central_flux != SX_FLUX_SPLIT || s.visc_order != s.central_order))
+        return SX_EUNSUPPORTED;
+    // bulk forcing: central path (the force is formed from the fused kernel's sums)
+    if (s.bulk_forcing && s.sensor) return SX_EUNSUPPORTED;
+    // KEEP-n: FP64, sensor off, one order for convective and viscous terms
+    if (s.central_flux == SX_FLUX_KEEP &&
+        (s.precision != SX_FP64 || s.sensor || s.visc_order != s.central_order))
+        return SX_EUNSUPPORTED;
     *ng_out = ng;
     return SX_OK;
 }
@@ -155,6 +171,7 @@ void sx_fill_kernel_params(const sx_grid& g, const sx_gas& gas, const sx_scheme&
     kg->dz = g.lz / g.nz;
     kg->dxi = 1.0 / kg->dx;
     kg->dzi = 1.0 / kg->dz;
+    kg->fpart = nullptr;
 
     kgas->gamma = gas.gamma;
     kgas->gm1 = gas.gamma - 1.0;
@@ -168,6 +185,18 @@ void sx_fill_kernel_params(const sx_grid& g, const sx_gas& gas, const sx_scheme&
     kgas->t_wall = gas.t_wall;
     kgas->pref = kgas->igM2;
     kgas->href = kgas->cp;
+    kgas->cvg = 1.0 / (kgas->gm1 * kgas->gM2);
+    kgas->keep_n = s.central_flux == SX_FLUX_KEEP ? s.keep_n : 0;
+    kgas->thermo = gas.thermo;
+    {
+        double tk = 1.0;
+        for (int k = 0; k < 5; ++k) {
+            const double a = gas.thermo ? gas.nasa[k] : (k == 0 ? gas.gamma / (gas.gamma - 1.0) : 0.0);
+            kgas->tcp[k] = a * tk;
+            kgas->tce[k] = (k == 0 ? a - 1.0 : a * tk) / (k + 1);
+            tk *= gas.thermo ? gas.t_ref : 1.0;
+        }
+    }
 
     ks->L = s.central_order / 2;
     ks->Lv = s.visc_order / 2;
@@ -177,6 +206,7 @@ void sx_fill_kernel_params(const sx_grid& g, const sx_gas& gas, const sx_scheme&
     ks->sensor_eps = s.sensor_eps;
     ks->weno_eps = s.weno_eps;
     ks->precision = s.precision;
+    ks->flux = s.central_flux;
 }
 
 // Metrics of one block on the host, uploaded; sets the KGrid pointers.
@@ -224,12 +254,17 @@ int sx_init(const sx_grid* grid, const sx_gas* gas, const sx_scheme* scheme, sx_
     }
     bool all_periodic = true;
     for (int f = 0; f < 6; ++f) all_periodic = all_periodic && g.bc[f] == SX_BC_PERIODIC;
-    h->pimg = all_periodic && !s.sensor && s.visc_order == s.central_order && g.nx >= 2 * ng &&
-              g.ny >= 2 * ng && g.nz >= 2 * ng;
+    h->pimg = all_periodic && !s.sensor && s.visc_order == s.central_order && !s.bulk_forcing &&
+              !gas->thermo &&
+              s.central_flux == SX_FLUX_SPLIT && g.nx >= 2 * ng && g.ny >= 2 * ng && g.nz >= 2 * ng;
 
     hipError_t e = sx_upload_metrics(g, h->ks.L, &h->d_metrics, &h->kg);
     if (e == hipSuccess)
         e = hipMalloc(&h->d_scratch, sizeof(double) * (sx::kReduceBlocks + 1) * sx::kDiagVals);
+    if (e == hipSuccess && s.bulk_forcing) {
+        e = hipMalloc(&h->d_force, sizeof(double) * sx::force_slots(g.nx, g.ny, g.nz));
+        h->kg.fpart = h->d_force;
+    }
     if (e == hipSuccess && s.sensor) {
         const long long ni = h->lay.interior;
         const long long nf[3] = {(long long)g.nz * g.ny * (g.nx + 1), (long long)g.nz * (g.ny + 1) * g.nx,
@@ -258,7 +293,7 @@ void sx_finalize(sx_handle* h)
 {
     if (!h) return;
     const sx::WenoBufs& b = h->wb;
-    for (void* p : {(void*)h->d_metrics, (void*)h->d_scratch, (void*)b.theta, (void*)b.f[0],
+    for (void* p : {(void*)h->d_metrics, (void*)h->d_scratch, (void*)h->d_force, (void*)b.theta, (void*)b.f[0],
                     (void*)b.f[1], (void*)b.f[2], (void*)b.flist[0], (void*)b.flist[1],
                     (void*)b.flist[2], (void*)b.dF[0], (void*)b.dF[1], (void*)b.dF[2],
                     (void*)b.nlist, (void*)b.counts, (void*)h->d_fcount})

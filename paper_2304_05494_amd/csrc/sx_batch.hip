@@ -405,7 +405,12 @@ int sx_init_batch(int nbox, const sx_grid* grids, const sx_gas* gases, const sx_
         ng = ngb;
     }
     // the persistent kernels are built for equal convective and viscous orders
-    if (scheme->visc_order != scheme->central_order) return SX_EUNSUPPORTED;
+    // and the split-form flux
+    if (scheme->visc_order != scheme->central_order || scheme->central_flux != SX_FLUX_SPLIT ||
+        scheme->bulk_forcing)
+        return SX_EUNSUPPORTED;
+    for (int b = 0; b < nbox; ++b)
+        if (gases[b].thermo) return SX_EUNSUPPORTED;
     sx_handle* h = new sx_handle();
     h->batch = true;
     h->scheme = *scheme;

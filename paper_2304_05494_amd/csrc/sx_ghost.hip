@@ -69,15 +69,22 @@ __global__ void __launch_bounds__(256) k_ghost(KGrid g, KGas gas, double* __rest
     const double rho = W[mi];
     const double ri = 1.0 / rho;
     const double u = W[g.sv + mi] * ri, v = W[2 * g.sv + mi] * ri, w = W[3 * g.sv + mi] * ri;
-    const double p = gas.gm1 * (W[4 * g.sv + mi] - 0.5 * rho * (u * u + v * v + w * w));
-    const double Tm = gas.gM2 * p * ri;
+    double p, Tm;
+    if (gas.thermo) {   // thermally perfect: T from the internal energy
+        Tm = tp_T_of_e(gas, W[4 * g.sv + mi] * ri - 0.5 * (u * u + v * v + w * w));
+        p = rho * Tm * gas.igM2;
+    } else {
+        p = gas.gm1 * (W[4 * g.sv + mi] - 0.5 * rho * (u * u + v * v + w * w));
+        Tm = gas.gM2 * p * ri;
+    }
     const double Tg = 2.0 * gas.t_wall - Tm;
     const double rg = gas.gM2 * p / Tg;
     W[gi] = rg;
     W[g.sv + gi] = -rg * u;
     W[2 * g.sv + gi] = -rg * v;
     W[3 * g.sv + gi] = -rg * w;
-    W[4 * g.sv + gi] = p / gas.gm1 + 0.5 * rg * (u * u + v * v + w * w);
+    const double eg = gas.thermo ? rg * gas.igM2 * tp_eR(gas, Tg) : p / gas.gm1;
+    W[4 * g.sv + gi] = eg + 0.5 * rg * (u * u + v * v + w * w);
 }
 
 hipError_t launch_ghost_fill(const KGrid& g, const KGas& gas, double* W, hipStream_t st)

@@ -22,6 +22,7 @@ struct KGrid {
     const double* eta_y;        // [ny] 1 / y_eta
     const double* eta_yy;       // [ny] -y_etaeta / y_eta^3
     const double* y_eta;        // [ny]
+    double* fpart;              // bulk forcing: one partial sum per workgroup (nullptr: off)
 };
 
 struct KGas {
@@ -36,7 +37,47 @@ struct KGas {
     double t_wall;
     double pref;                // reference pressure 1/(gamma M^2) (FP32-flux shift)
     double href;                // reference enthalpy c_p (FP32-flux shift)
+    double cvg;                 // 1/((gamma-1) gamma M^2): KEEP-n energy term
+    int keep_n;                 // KEEP-n series terms beyond the first (< 0: exact)
+    int thermo;                 // 1: thermally perfect gas
+    double tcp[5];              // c_p / R_g = sum_k tcp[k] T^k  (NASA a_k t_ref^k)
+    double tce[5];              // e / R_g   = sum_k tce[k] T^(k+1)
 };
+
+// Thermally perfect gas (gas constant R_g = igM2): c_p / R_g and its
+// T-derivative, e / R_g, and T of a specific internal energy by Newton's
+// method on e(T) (started from the T = 1 heat capacity, stopped at a
+// relative step of 1e-15).
+__device__ __forceinline__ double tp_cpR(const KGas& g, double T)
+{
+    return (((g.tcp[4] * T + g.tcp[3]) * T + g.tcp[2]) * T + g.tcp[1]) * T + g.tcp[0];
+}
+__device__ __forceinline__ double tp_dcpR(const KGas& g, double T)
+{
+    return ((4.0 * g.tcp[4] * T + 3.0 * g.tcp[3]) * T + 2.0 * g.tcp[2]) * T + g.tcp[1];
+}
+__device__ __forceinline__ double tp_eR(const KGas& g, double T)
+{
+    return ((((g.tce[4] * T + g.tce[3]) * T + g.tce[2]) * T + g.tce[1]) * T + g.tce[0]) * T;
+}
+__device__ __forceinline__ double tp_T_of_e(const KGas& g, double e)
+{
+    const double eR = e / g.igM2;
+    double T = eR / (tp_cpR(g, 1.0) - 1.0);
+    for (int it = 0; it < 100; ++it) {
+        const double dT = (tp_eR(g, T) - eR) / (tp_cpR(g, T) - 1.0);
+        T -= dT;
+        if (fabs(dT) <= 1e-15 * fabs(T)) break;
+    }
+    return T;
+}
+// ratio of specific heats at T
+__device__ __forceinline__ double tp_gamma(const KGas& g, double T)
+{
+    if (!g.thermo) return g.gamma;
+    const double c = tp_cpR(g, T);
+    return c / (c - 1.0);
+}
 
 struct KScheme {
     int L;                      // central half-order
@@ -45,6 +86,7 @@ struct KScheme {
     int sensor;
     double sensor_thr, sensor_eps, weno_eps;
     int precision;              // SX_FP64 or SX_FP32_FLUX
+    int flux;                   // SX_FLUX_SPLIT or SX_FLUX_KEEP
 };
 
 // Central first-derivative weights a_l (D1 f = sum a_l (f_{+l} - f_{-l})) and
@@ -109,6 +151,13 @@ struct BatchLaunch {
     int nwg;             // workgroups of the persistent grid
 };
 hipError_t launch_batch(const KScheme& sc, int variant, const BatchLaunch& b, hipStream_t st);
+// Slots of the bulk-forcing partial array of a block: one per workgroup of
+// any fused launch (tiles of at least 32 x 4 columns, chunks of at least one
+// plane), plus the force value.
+inline long long force_slots(int nx, int ny, int nz)
+{
+    return (long long)((nx + 31) / 32) * ((ny + 3) / 4) * nz + 2;
+}
 hipError_t launch_set_value(double* p, double v, hipStream_t st);
 int batch_occupancy(const KScheme& sc, int variant);   // resident workgroups per CU
 void batch_tile_shape(const KScheme& sc, int variant, int* tx, int* ty);

@@ -69,12 +69,19 @@ __global__ void __launch_bounds__(RB) k_diag_partial(KGrid g, KGas gas, const do
         const double ri = 1.0 / w[0];
         const double u = w[1] * ri, v = w[2] * ri, ww = w[3] * ri;
         const double q2 = u * u + v * v + ww * ww;
-        const double p = gas.gm1 * (w[4] - 0.5 * w[0] * q2);
+        double p, gm = gas.gamma;
+        if (gas.thermo) {
+            const double T = tp_T_of_e(gas, w[4] * ri - 0.5 * q2);
+            p = w[0] * T * gas.igM2;
+            gm = tp_gamma(gas, T);
+        } else {
+            p = gas.gm1 * (w[4] - 0.5 * w[0] * q2);
+        }
         acc[D_KE] += vol * (0.5 * w[0] * q2);
         if (!(w[0] > 0.0) || !(p > 0.0)) acc[D_NONPHYS] += 1.0;
         acc[D_RMIN] = fmin(acc[D_RMIN], w[0]);
         acc[D_PMIN] = fmin(acc[D_PMIN], p);
-        if (w[0] > 0.0 && p > 0.0) acc[D_MACH] = fmax(acc[D_MACH], sqrt(q2 * w[0] / (gas.gamma * p)));
+        if (w[0] > 0.0 && p > 0.0) acc[D_MACH] = fmax(acc[D_MACH], sqrt(q2 * w[0] / (gm * p)));
     }
 #pragma unroll
     for (int q = 0; q < kDiagVals; ++q) red[q][threadIdx.x] = acc[q];
@@ -125,13 +132,20 @@ __global__ void __launch_bounds__(RB) k_rate_partial(KGrid g, KGas gas, const do
         const double rho = W[n];
         const double ri = 1.0 / rho;
         const double u = W[g.sv + n] * ri, v = W[2 * g.sv + n] * ri, w = W[3 * g.sv + n] * ri;
-        const double p = gas.gm1 * (W[4 * g.sv + n] - 0.5 * rho * (u * u + v * v + w * w));
-        const double cs = sqrt(gas.gamma * p * ri);
-        const double T_ = gas.gM2 * p * ri;
+        double p, T_, gm = gas.gamma;
+        if (gas.thermo) {
+            T_ = tp_T_of_e(gas, W[4 * g.sv + n] * ri - 0.5 * (u * u + v * v + w * w));
+            p = rho * T_ * gas.igM2;
+            gm = tp_gamma(gas, T_);
+        } else {
+            p = gas.gm1 * (W[4 * g.sv + n] - 0.5 * rho * (u * u + v * v + w * w));
+            T_ = gas.gM2 * p * ri;
+        }
+        const double cs = sqrt(gm * p * ri);
         const double mu = pow(T_, gas.s) * gas.ire;
         const double hy = g.y_eta[j];
         const double conv = (fabs(u) + cs) * g.dxi + (fabs(v) + cs) / hy + (fabs(w) + cs) * g.dzi;
-        const double visc = 2.0 * gas.gamma * mu * ri * gas.ipr *
+        const double visc = 2.0 * gm * mu * ri * gas.ipr *
                             (g.dxi * g.dxi + 1.0 / (hy * hy) + g.dzi * g.dzi);
         a = fmax(a, conv + visc);
     }
@@ -166,3 +180,4 @@ hipError_t launch_max_rate(const KGrid& g, const KGas& gas, const double* W, dou
 }
 
 }  // namespace sx
+

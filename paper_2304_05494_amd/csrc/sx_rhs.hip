@@ -60,6 +60,10 @@ __device__ __forceinline__ double rcp(double x)
 
 __device__ __forceinline__ void sched_fence() { __builtin_amdgcn_sched_barrier(0); }
 
+// fused multiply-add in the arithmetic type (FP32 stays FP32)
+__device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 template <int S, typename R>
 __device__ __forceinline__ R d1(const R (&f)[2 * S + 1])
 {
@@ -187,15 +191,21 @@ struct Layout<float> {
     static constexpr bool SEP_H = false;
 };
 
+// 16-byte vector of two doubles with its natural alignment, so that LDS
+// accesses at a run-time record index stay single 128-bit operations (split
+// into two 64-bit halves, records 48 bytes apart would fall on the same
+// banks two lanes at a time).
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
 template <typename R>
 __device__ __forceinline__ void plane_write(R* so, R* sH, int q, double rho, double u, double v,
                                             double w, double T, double p, double H)
 {
     if constexpr (std::is_same<R, double>::value) {
-        double2* rec = reinterpret_cast<double2*>(so + 6 * q);
-        rec[0] = make_double2(u, v);
-        rec[1] = make_double2(w, T);
-        rec[2] = make_double2(rho, p);
+        dbl2* rec = reinterpret_cast<dbl2*>(so + 6 * q);
+        rec[0] = dbl2{u, v};
+        rec[1] = dbl2{w, T};
+        rec[2] = dbl2{rho, p};
         sH[q] = H;
     } else {
         R* rec = so + 7 * q;
@@ -208,12 +218,26 @@ template <typename R>
 __device__ __forceinline__ Node<R> plane_read(const R* so, const R* sH, int q)
 {
     if constexpr (std::is_same<R, double>::value) {
-        const double2* rec = reinterpret_cast<const double2*>(so + 6 * q);
-        const double2 a = rec[0], b = rec[1], e = rec[2];
+        const dbl2* rec = reinterpret_cast<const dbl2*>(so + 6 * q);
+        const dbl2 a = rec[0], b = rec[1], e = rec[2];
         return Node<double>{e.x, a.x, a.y, b.x, b.y, e.y, sH[q]};
     } else {
         const R* rec = so + 7 * q;
         return Node<R>{rec[0], rec[1], rec[2], rec[3], rec[4], rec[5], rec[6]};
+    }
+}
+
+// u and v of plane record q (FP64: one 128-bit load)
+template <typename R>
+__device__ __forceinline__ void plane_uv(const R* so, int q, R& u, R& v)
+{
+    if constexpr (std::is_same<R, double>::value) {
+        const dbl2 a = reinterpret_cast<const dbl2*>(so + 6 * q)[0];
+        u = a.x;
+        v = a.y;
+    } else {
+        u = so[7 * q + 1];
+        v = so[7 * q + 2];
     }
 }
 
@@ -222,10 +246,10 @@ __device__ __forceinline__ void ring_write(R* z, double rho, double u, double v,
                                            double T, double p, double H)
 {
     if constexpr (std::is_same<R, double>::value) {
-        double2* rec = reinterpret_cast<double2*>(z);
-        rec[0] = make_double2(u, v);
-        rec[1] = make_double2(w, T);
-        rec[2] = make_double2(rho, H);
+        dbl2* rec = reinterpret_cast<dbl2*>(z);
+        rec[0] = dbl2{u, v};
+        rec[1] = dbl2{w, T};
+        rec[2] = dbl2{rho, H};
         (void)p;
     } else {
         z[0] = R(rho); z[1] = R(u); z[2] = R(v); z[3] = R(w); z[4] = R(T); z[5] = R(p); z[6] = R(H);
@@ -236,8 +260,8 @@ template <typename R>
 __device__ __forceinline__ Node<R> ring_read(const R* z, R igM2)
 {
     if constexpr (std::is_same<R, double>::value) {
-        const double2* rec = reinterpret_cast<const double2*>(z);
-        const double2 a = rec[0], b = rec[1], e = rec[2];
+        const dbl2* rec = reinterpret_cast<const dbl2*>(z);
+        const dbl2 a = rec[0], b = rec[1], e = rec[2];
         return Node<double>{e.x, a.x, a.y, b.x, b.y, e.x * b.y * igM2, e.y};
     } else {
         return Node<R>{z[0], z[1], z[2], z[3], z[4], z[5], z[6]};
@@ -253,9 +277,52 @@ __device__ __forceinline__ Node<R> ring_read(const R* z, R igM2)
 // to acc and returns first derivatives gd = (u, v, w, T)_n and the pure
 // second derivatives dd = (u, v, w, T)_nn (sc: metric 1/h or eta_y;
 // sc2 = sc^2; scy = eta_yy along y, 0 otherwise).
-template <int SC, int SV, int D, bool CONV, bool VISC, typename R, typename Get>
+// KEEP-n two-point flux (FP64). The entropy-conserving, kinetic-energy
+// preserving pair flux of nodes A, B along direction D:
+//   F_rho = rho_ln (ud_A + ud_B)/2,  F_mom = F_rho (u_A + u_B)/2 + (p_A + p_B)/2 e_D,
+//   F_E   = F_rho (1/((gamma-1) b_ln) + u_A.u_B/2) + (p_A ud_B + p_B ud_A)/2,
+// b = rho/p, x_ln the logarithmic mean. With b = gamma M^2 / T,
+// 1/((gamma-1) b_ln) = T_A T_B / ((gamma-1) gamma M^2) * 1/T_ln, and
+// 1/x_ln = 2/(x_A+x_B) sum_{m=0..n} xi^(2m)/(2m+1), xi = (x_B-x_A)/(x_B+x_A),
+// cut after n terms (n < 0: the exact mean; its series up to m = 16 where
+// |xi| < 0.1, the logarithms elsewhere).
+__device__ __forceinline__ double keep_inv_log_mean(double a, double b, int n)
+{
+    constexpr double inv_odd[17] = {1.0,        1.0 / 3.0,  1.0 / 5.0,  1.0 / 7.0,  1.0 / 9.0,  1.0 / 11.0,
+                                    1.0 / 13.0, 1.0 / 15.0, 1.0 / 17.0, 1.0 / 19.0, 1.0 / 21.0, 1.0 / 23.0,
+                                    1.0 / 25.0, 1.0 / 27.0, 1.0 / 29.0, 1.0 / 31.0, 1.0 / 33.0};
+    const double rs = rcp(a + b);
+    const double xi = (b - a) * rs;
+    if (n < 0) {
+        if (fabs(xi) >= 0.1) return (log(b) - log(a)) / (b - a);
+        n = 16;
+    }
+    const double x2 = xi * xi;
+    double S = inv_odd[n];
+    for (int m = n - 1; m >= 0; --m) S = __builtin_fma(S, x2, inv_odd[m]);
+    return 2.0 * rs * S;
+}
+
+template <int D>
+__device__ __forceinline__ void keep_pair(const Node<double>& A, const Node<double>& B, const KGas& gas,
+                                          double (&F)[NV])
+{
+    const double udA = D == 0 ? A.u : (D == 1 ? A.v : A.w);
+    const double udB = D == 0 ? B.u : (D == 1 ? B.v : B.w);
+    const double frho = 0.5 * (udA + udB) * rcp(keep_inv_log_mean(A.r, B.r, gas.keep_n));
+    const double uu = A.u * B.u + A.v * B.v + A.w * B.w;
+    const double K = gas.cvg * (A.T * B.T) * keep_inv_log_mean(A.T, B.T, gas.keep_n) + 0.5 * uu;
+    F[0] = frho;
+    F[1] = frho * (0.5 * (A.u + B.u));
+    F[2] = frho * (0.5 * (A.v + B.v));
+    F[3] = frho * (0.5 * (A.w + B.w));
+    F[1 + D] += 0.5 * (A.p + B.p);
+    F[4] = frho * K + 0.5 * (A.p * udB + B.p * udA);
+}
+
+template <int SC, int SV, int D, bool CONV, bool VISC, bool KEEP = false, typename R, typename Get>
 __device__ __forceinline__ void stencil_dir(Get get, R sc, R sc2, R scy, R (&acc)[NV], R (&gd)[4],
-                                            R (&dd)[4])
+                                            R (&dd)[4], const KGas* kgas = nullptr)
 {
     // convective pairs up to SC, viscous differences up to SV
     constexpr int SL = CONV && VISC ? Halo<SC, SV>::S : (CONV ? SC : SV);
@@ -265,18 +332,33 @@ __device__ __forceinline__ void stencil_dir(Get get, R sc, R sc2, R scy, R (&acc
 #pragma unroll
     for (int l = 1; l <= SL; ++l) {
         const Node<R> M = get(-l), P = get(l);
-        if (CONV && l <= SC) {
+        if constexpr (KEEP) {
+            if (CONV && l <= SC) {
+                // F(C, P) - F(M, C) with the KEEP-n pair flux
+                double Fp[NV], Fm[NV];
+                keep_pair<D>(C, P, *kgas, Fp);
+                keep_pair<D>(M, C, *kgas, Fm);
+                const double c2 = 2.0 * Coef<SC>::a[l];
+                f0 += c2 * (Fp[0] - Fm[0]);
+                f1 += c2 * (Fp[1] - Fm[1]);
+                f2 += c2 * (Fp[2] - Fm[2]);
+                f3 += c2 * (Fp[3] - Fm[3]);
+                f4 += c2 * (Fp[4] - Fm[4]);
+            }
+        } else if (CONV && l <= SC) {
             const R cl = R(0.25 * Coef<SC>::a[l]);
             const R udC = D == 0 ? C.u : (D == 1 ? C.v : C.w);
             const R udP = D == 0 ? P.u : (D == 1 ? P.v : P.w);
             const R udM = D == 0 ? M.u : (D == 1 ? M.v : M.w);
             const R mp = cl * (C.r + P.r) * (udC + udP);    // pair (C, P), +
             const R mm = cl * (M.r + C.r) * (udM + udC);    // pair (M, C), -
-            f0 += R(2) * (mp - mm);
-            f1 += mp * (C.u + P.u) - mm * (M.u + C.u);
-            f2 += mp * (C.v + P.v) - mm * (M.v + C.v);
-            f3 += mp * (C.w + P.w) - mm * (M.w + C.w);
-            f4 += mp * (C.H + P.H) - mm * (M.H + C.H);
+            // mp (C.phi + P.phi) - mm (M.phi + C.phi): the C.phi parts of all
+            // pairs sum to C.phi (f0 / 2), added after the loop
+            f0 += mp - mm;
+            f1 = fmar(mp, P.u, fmar(-mm, M.u, f1));
+            f2 = fmar(mp, P.v, fmar(-mm, M.v, f2));
+            f3 = fmar(mp, P.w, fmar(-mm, M.w, f3));
+            f4 = fmar(mp, P.H, fmar(-mm, M.H, f4));
             fp += (R(4) * cl) * (P.p - M.p);
         }
         if (VISC && l <= SV) {
@@ -292,9 +374,16 @@ __device__ __forceinline__ void stencil_dir(Get get, R sc, R sc2, R scy, R (&acc
         }
     }
     if (CONV) {
-        if (D == 0) f1 += fp;
-        if (D == 1) f2 += fp;
-        if (D == 2) f3 += fp;
+        if constexpr (!KEEP) {
+            f1 = fmar(C.u, f0, f1);
+            f2 = fmar(C.v, f0, f2);
+            f3 = fmar(C.w, f0, f3);
+            f4 = fmar(C.H, f0, f4);
+            f0 *= R(2);
+            if (D == 0) f1 += fp;
+            if (D == 1) f2 += fp;
+            if (D == 2) f3 += fp;
+        }
         acc[0] -= sc * f0;
         acc[1] -= sc * f1;
         acc[2] -= sc * f2;
@@ -346,6 +435,7 @@ struct Smem {
     R sH[Layout<R>::SEP_H ? HP : 1];                                // output plane enthalpy
     R gyl[2][TY][HX];                                               // D_y u, D_y v of plane k
     __attribute__((aligned(16))) R zring[Q * NT * Layout<R>::ZREC]; // column records
+    double fred[NT];                                                // bulk-forcing partial sums
 };
 
 // March one column tile (i0, j0) of one block over planes [k0, k1).
@@ -363,7 +453,25 @@ __device__ __forceinline__ void sto(T* base, unsigned bo, T v)
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + bo) = v;
 }
 
-template <int SC, int SV, int TX, int TY, typename R, bool UPD, bool PIMG>
+// Bulk forcing: the workgroup's sum of V R_rhou over its output nodes,
+// written to its slot of g.fpart (fixed tree order). Every thread of the
+// workgroup calls this; the first n threads contribute v.
+template <int NTH>
+__device__ __forceinline__ void force_partial(double* red, int n, double v, const KGrid& g)
+{
+    __syncthreads();
+    if ((int)threadIdx.x < n) red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = n / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        g.fpart[blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z)] = red[0];
+    (void)NTH;
+}
+
+template <int SC, int SV, int TX, int TY, typename R, bool UPD, bool PIMG, int VAR = 0>
 __device__ __forceinline__ void march(Smem<Halo<SC, SV>::S, TX, TY, R>& sm, const double* __restrict__ W,
                                       double* __restrict__ out, double* __restrict__ Rp,
                                       const KGrid& g, const KGas& gas, const StepCoef& sc,
@@ -371,6 +479,8 @@ __device__ __forceinline__ void march(Smem<Halo<SC, SV>::S, TX, TY, R>& sm, cons
 {
     const unsigned mask = UPD ? (unsigned)SX_ALL : mask_in;   // an update always takes every term
     constexpr int S = Halo<SC, SV>::S;
+    constexpr bool THERMO = VAR == 2;   // thermally perfect gas (the KEEP-n flux runs split only)
+    static_assert(VAR != 1, "KEEP-n runs in the split march");
     using L = Layout<R>;
     constexpr int NT = TX * TY;
     constexpr int HX = TX + 2 * S, HY = TY + 2 * S, HP = HX * HY;
@@ -394,9 +504,11 @@ __device__ __forceinline__ void march(Smem<Halo<SC, SV>::S, TX, TY, R>& sm, cons
     const R eyy = active ? R(g.eta_yy[j]) : R(0);
     const R dxi = R(g.dxi), dzi = R(g.dzi);
     const R igM2 = R(gas.igM2);
-    const long long col = g.base + (long long)j * g.sy + i;   // this column at k = 0
     static_assert(64 % TX == 0, "every row of the tile lies in one wave");
     const R eyr = j < g.ny ? R(g.eta_y[j]) : R(0);            // eta_y of this row
+    // bulk forcing: cell volume of this column's nodes, running sum of V R_rhou
+    const double fvol = active && g.fpart ? g.dx * g.y_eta[j] * g.dz : 0.0;
+    double fsum = 0.0;
 
     R m0[Q], m1[Q], m2[Q];   // D_x w, D_y w, D_x u + D_y v of this column
 #pragma unroll
@@ -404,46 +516,44 @@ __device__ __forceinline__ void march(Smem<Halo<SC, SV>::S, TX, TY, R>& sm, cons
 
     // Global accesses: per-variable base pointer plus a 32-bit byte offset
     // (in-plane part per thread, plane part uniform); see march_split.
-    const unsigned colbo = (unsigned)(col * 8);
-    const unsigned jibo = (unsigned)(((long long)j * g.nx + i) * 8);
+    // inactive threads (ragged tiles) load the nearest interior column; only
+    // active threads store
+    const int ic = min(i, g.nx - 1), jc = min(j, g.ny - 1);
+    const unsigned colbo = (unsigned)((g.base + (long long)jc * g.sy + ic) * 8);
+    const unsigned jibo = (unsigned)(((long long)jc * g.nx + ic) * 8);
     auto kbo = [&](int k) { return (unsigned)((long long)k * g.sz * 8); };
     auto kbr = [&](int k) { return (unsigned)((long long)k * g.ny * g.nx * 8); };
+    // Halo points outside the ghosted block (ragged tiles, the unused tail
+    // of the last round) load the nearest ghosted node instead: valid data,
+    // no branch; no active output reads them.
     unsigned hbo[NPT];
-    bool hok[NPT];
 #pragma unroll
     for (int a = 0; a < NPT; ++a) {
         const int q = tid + a * NT;
         const int hx = q % HX, hy = q / HX;
-        const int gi = i0 - S + hx, gj = j0 - S + hy;
-        hok[a] = q < HP && gi >= -g.ng && gi < g.nx + g.ng && gj >= -g.ng && gj < g.ny + g.ng;
-        hbo[a] = hok[a] ? (unsigned)((g.base + (long long)gj * g.sy + gi) * 8) : 0u;
+        const int gi = min(max(i0 - S + hx, -g.ng), g.nx + g.ng - 1);
+        const int gj = min(max(j0 - S + hy, -g.ng), g.ny + g.ng - 1);
+        hbo[a] = (unsigned)((g.base + (long long)gj * g.sy + gi) * 8);
     }
     auto fetch = [&](PlaneFetch<NPT>& f, int k, int nvar) {
         const unsigned kb = kbo(k);
 #pragma unroll
         for (int a = 0; a < NPT; ++a) {
-            f.q[a][0] = 1.0;
-            f.q[a][1] = f.q[a][2] = f.q[a][3] = 0.0;
-            f.q[a][4] = 1.0;
-            if (hok[a]) {
-                const unsigned bo = hbo[a] + kb;
+            const unsigned bo = hbo[a] + kb;
 #pragma unroll
-                for (int v = 0; v < 5; ++v)
-                    if (v < nvar) f.q[a][v] = ldo(W + v * g.sv, bo);
-            }
+            for (int v = 0; v < 5; ++v)
+                if (v < nvar) f.q[a][v] = ldo(W + v * g.sv, bo);
         }
     };
     auto fetch_col = [&](double (&cq)[5], int k) {
         const unsigned bn = colbo + kbo(k);
 #pragma unroll
-        for (int v = 0; v < 5; ++v) cq[v] = active ? ldo(W + v * g.sv, bn) : (v == 0 ? 1.0 : 0.0);
+        for (int v = 0; v < 5; ++v) cq[v] = ldo(W + v * g.sv, bn);
     };
-    double wc[5], rp[5];   // centre state and RK register of the next output node
+    double wc[5] = {}, rp[5] = {};   // centre state and RK register of the next output node
     auto fetch_centre = [&](int k) {
         const unsigned bn = colbo + kbo(k), bm = jibo + kbr(k);
-#pragma unroll
-        for (int v = 0; v < 5; ++v) wc[v] = rp[v] = 0.0;
-        if (UPD && active) {
+        if (UPD) {
 #pragma unroll
             for (int v = 0; v < 5; ++v) wc[v] = ldo(W + v * g.sv, bn);
             if (sc.read_prev) {
@@ -473,8 +583,14 @@ __device__ __forceinline__ void march(Smem<Halo<SC, SV>::S, TX, TY, R>& sm, cons
         u = w5[1] * ri;
         v = w5[2] * ri;
         w = w5[3] * ri;
-        const double pr = gas.gm1 * (w5[4] - 0.5 * rho * (u * u + v * v + w * w));
-        T = gas.gM2 * pr * ri;
+        double pr;
+        if constexpr (THERMO) {   // thermally perfect: T from the internal energy
+            T = tp_T_of_e(gas, w5[4] * ri - 0.5 * (u * u + v * v + w * w));
+            pr = rho * T * gas.igM2;
+        } else {
+            pr = gas.gm1 * (w5[4] - 0.5 * rho * (u * u + v * v + w * w));
+            T = gas.gM2 * pr * ri;
+        }
         H = (w5[4] + pr) * ri - href;
         p = pr - pref;
     };
@@ -607,9 +723,11 @@ __device__ __forceinline__ void march(Smem<Halo<SC, SV>::S, TX, TY, R>& sm, cons
             R su = 0, sv = 0;
 #pragma unroll
             for (int l = 1; l <= SV; ++l) {
-                const int up = L::PREC * ((ty + S + l) * HX + hx), dn = L::PREC * ((ty + S - l) * HX + hx);
-                su += R(Coef<SV>::a[l]) * (so[up + L::OU] - so[dn + L::OU]);
-                sv += R(Coef<SV>::a[l]) * (so[up + L::OV] - so[dn + L::OV]);
+                R uu, vu, ud, vd;
+                plane_uv<R>(so, (ty + S + l) * HX + hx, uu, vu);
+                plane_uv<R>(so, (ty + S - l) * HX + hx, ud, vd);
+                su += R(Coef<SV>::a[l]) * (uu - ud);
+                sv += R(Coef<SV>::a[l]) * (vu - vd);
             }
             gyl[0][ty][hx] = eyr * su;
             gyl[1][ty][hx] = eyr * sv;
@@ -627,11 +745,18 @@ __device__ __forceinline__ void march(Smem<Halo<SC, SV>::S, TX, TY, R>& sm, cons
             const bool visc = mask & SX_VISC;
             const Node<R> Cz = znode(slot_k);
             const R uc = Cz.u, vc = Cz.v, wc_ = Cz.w, Tc = Cz.T;
-            R mu = 0, kcd = 0, smt = 0;
+            R mu = 0, kcd = 0, smt = 0, skt = 0;
             if (visc) {
                 mu = visc_pow<R>(Tc, gas) * R(gas.ire);
-                kcd = mu * R(gas.cp * gas.ipr);
                 smt = R(gas.s) * rcpr<R>(Tc);
+                if constexpr (THERMO) {   // k = mu c_p(T) / Pr, grad k = k (s/T + c_p'/c_p) grad T
+                    const double cpr = tp_cpR(gas, double(Tc));
+                    kcd = mu * R(gas.igM2 * cpr * gas.ipr);
+                    skt = smt + R(tp_dcpR(gas, double(Tc)) / cpr);
+                } else {
+                    kcd = mu * R(gas.cp * gas.ipr);
+                    skt = smt;
+                }
             }
             R gx[4] = {0, 0, 0, 0}, gy[4] = {0, 0, 0, 0}, gz[4] = {0, 0, 0, 0}, dd[4];
             auto getx = [&](int t) { return plane_read<R>(so, sH, c + t); };
@@ -697,13 +822,14 @@ __device__ __forceinline__ void march(Smem<Halo<SC, SV>::S, TX, TY, R>& sm, cons
                 acc[1] += N0;
                 acc[2] += N1;
                 acc[3] += N2;
-                acc[4] += uc * N0 + vc * N1 + wc_ * N2 + diss + (smt * kcd) * (Tx * Tx + Ty * Ty + Tz * Tz);
+                acc[4] += uc * N0 + vc * N1 + wc_ * N2 + diss + (skt * kcd) * (Tx * Tx + Ty * Ty + Tz * Tz);
             }
             pend_k = k;
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 double r = double(acc[v]);
                 if (f32 && v == 4) r += accE_shift;
+                if (v == 1) fsum = __builtin_fma(fvol, r, fsum);
                 pend[v] = r;
                 if (UPD) {
                     double nv = __builtin_fma(sc.cg, r, wcur[v]);
@@ -717,6 +843,7 @@ __device__ __forceinline__ void march(Smem<Halo<SC, SV>::S, TX, TY, R>& sm, cons
         __syncthreads();
     }
     flush();
+    if (g.fpart) force_partial<NT>(sm.fred, NT, fsum, g);
 }
 
 // LDS working set of the role-split march: the non-split set plus the
@@ -733,6 +860,7 @@ struct SmemSplit {
     __attribute__((aligned(16))) R zring[Q * NR * Layout<R>::ZREC]; // column records
     R xch[NV][NR];                                                  // viscous RHS of plane k
     R vmu[NR];                                                      // viscosity of plane k (role 1 -> 0)
+    double fred[NR];                                                // bulk-forcing partial sums
 };
 
 // Role-split march: the workgroup holds two threads per tile column. Role 0
@@ -752,7 +880,7 @@ struct SmemSplit {
 // was last read before barrier 2 of plane k, the hand-over arrays are read
 // by role 0 before it reaches barrier 1 of plane k+1 and written again by
 // role 1 only after it, and the D_y rows are private to one wave.
-template <int SC, int SV, int TX, int TY, typename R, bool UPD, bool PIMG>
+template <int SC, int SV, int TX, int TY, typename R, bool UPD, bool PIMG, int VAR = 0>
 __device__ __forceinline__ void march_split(SmemSplit<Halo<SC, SV>::S, TX, TY, R>& sm, const double* __restrict__ W,
                                             double* __restrict__ out, double* __restrict__ Rp,
                                             const KGrid& g, const KGas& gas, const StepCoef& sc,
@@ -760,6 +888,8 @@ __device__ __forceinline__ void march_split(SmemSplit<Halo<SC, SV>::S, TX, TY, R
 {
     const unsigned mask = UPD ? (unsigned)SX_ALL : mask_in;
     constexpr int S = Halo<SC, SV>::S;
+    // variants: 1 KEEP-n central flux, 2 thermally perfect gas
+    constexpr bool KEEP = VAR == 1, THERMO = VAR == 2;
     using L = Layout<R>;
     constexpr int NR = TX * TY;
     constexpr int HX = TX + 2 * S, HP = HX * (TY + 2 * S);
@@ -787,7 +917,6 @@ __device__ __forceinline__ void march_split(SmemSplit<Halo<SC, SV>::S, TX, TY, R
     const R eyy = active ? R(g.eta_yy[j]) : R(0);
     const R dxi = R(g.dxi), dzi = R(g.dzi);
     const R igM2 = R(gas.igM2);
-    const long long col = g.base + (long long)j * g.sy + i;
     const bool visc = mask & SX_VISC;
 
     // Global accesses take a per-variable base pointer (uniform, scalar
@@ -795,33 +924,33 @@ __device__ __forceinline__ void march_split(SmemSplit<Halo<SC, SV>::S, TX, TY, R
     // thread, the plane part k*sz is uniform, so each load or store costs
     // one vector add. The host keeps every array of one variable below
     // 4 GiB.
-    const unsigned colbo = (unsigned)(col * 8);
-    const unsigned jibo = (unsigned)(((long long)j * g.nx + i) * 8);
+    // inactive threads (ragged tiles) load the nearest interior column; only
+    // active threads store
+    const int ic = min(i, g.nx - 1), jc = min(j, g.ny - 1);
+    const unsigned colbo = (unsigned)((g.base + (long long)jc * g.sy + ic) * 8);
+    const unsigned jibo = (unsigned)(((long long)jc * g.nx + ic) * 8);
     auto kbo = [&](int k) { return (unsigned)((long long)k * g.sz * 8); };
     auto kbr = [&](int k) { return (unsigned)((long long)k * g.ny * g.nx * 8); };
+    // Halo points outside the ghosted block (ragged tiles, the unused tail
+    // of the last round) load the nearest ghosted node instead: valid data,
+    // no branch; no active output reads them.
     unsigned hbo[NPT];
-    bool hok[NPT];
 #pragma unroll
     for (int a = 0; a < NPT; ++a) {
         const int q = tid + a * NR;
         const int hx = q % HX, hy = q / HX;
-        const int gi = i0 - S + hx, gj = j0 - S + hy;
-        hok[a] = q < HP && gi >= -g.ng && gi < g.nx + g.ng && gj >= -g.ng && gj < g.ny + g.ng;
-        hbo[a] = hok[a] ? (unsigned)((g.base + (long long)gj * g.sy + gi) * 8) : 0u;
+        const int gi = min(max(i0 - S + hx, -g.ng), g.nx + g.ng - 1);
+        const int gj = min(max(j0 - S + hy, -g.ng), g.ny + g.ng - 1);
+        hbo[a] = (unsigned)((g.base + (long long)gj * g.sy + gi) * 8);
     }
     auto fetch = [&](PlaneFetch<NPT>& f, int k, int nvar) {
         const unsigned kb = kbo(k);
 #pragma unroll
         for (int a = 0; a < NPT; ++a) {
-            f.q[a][0] = 1.0;
-            f.q[a][1] = f.q[a][2] = f.q[a][3] = 0.0;
-            f.q[a][4] = 1.0;
-            if (hok[a]) {
-                const unsigned bo = hbo[a] + kb;
+            const unsigned bo = hbo[a] + kb;
 #pragma unroll
-                for (int v = 0; v < 5; ++v)
-                    if (v < nvar) f.q[a][v] = ldo(W + v * g.sv, bo);
-            }
+            for (int v = 0; v < 5; ++v)
+                if (v < nvar) f.q[a][v] = ldo(W + v * g.sv, bo);
         }
     };
     auto prims = [&](const double* w5, double& rho, double& u, double& v, double& w, double& T,
@@ -831,23 +960,30 @@ __device__ __forceinline__ void march_split(SmemSplit<Halo<SC, SV>::S, TX, TY, R
         u = w5[1] * ri;
         v = w5[2] * ri;
         w = w5[3] * ri;
-        const double pr = gas.gm1 * (w5[4] - 0.5 * rho * (u * u + v * v + w * w));
-        T = gas.gM2 * pr * ri;
+        double pr;
+        if constexpr (THERMO) {   // thermally perfect: T from the internal energy
+            T = tp_T_of_e(gas, w5[4] * ri - 0.5 * (u * u + v * v + w * w));
+            pr = rho * T * gas.igM2;
+        } else {
+            pr = gas.gm1 * (w5[4] - 0.5 * rho * (u * u + v * v + w * w));
+            T = gas.gM2 * pr * ri;
+        }
         H = (w5[4] + pr) * ri - href;
         p = pr - pref;
     };
     auto znode = [&](int slot) { return ring_read<R>(zring + L::ZREC * (slot * NR + tid), igM2); };
     auto getx = [&](int t) { return plane_read<R>(so, sH, c + t); };
     auto gety = [&](int t) { return plane_read<R>(so, sH, c + t * HX); };
+    // bulk forcing: cell volume of this column's nodes, running sum of V R_rhou (role 0)
+    const double fvol = active && g.fpart ? g.dx * g.y_eta[j] * g.dz : 0.0;
+    double fsum = 0.0;
 
     if (role == 0) {
         // ---- convective terms, column ring, update ----------------------
-        double wc[5], rp[5];
+        double wc[5] = {}, rp[5] = {};
         auto fetch_centre = [&](int k) {
             const unsigned bn = colbo + kbo(k), bm = jibo + kbr(k);
-#pragma unroll
-            for (int v = 0; v < 5; ++v) wc[v] = rp[v] = 0.0;
-            if (UPD && active) {
+            if (UPD) {
 #pragma unroll
                 for (int v = 0; v < 5; ++v) wc[v] = ldo(W + v * g.sv, bn);
                 if (sc.read_prev) {
@@ -934,9 +1070,11 @@ __device__ __forceinline__ void march_split(SmemSplit<Halo<SC, SV>::S, TX, TY, R
                 R su = 0, sv = 0;
 #pragma unroll
                 for (int l = 1; l <= SV; ++l) {
-                    const int up = L::PREC * ((ty + S + l) * HX + hx), dn = L::PREC * ((ty + S - l) * HX + hx);
-                    su += R(Coef<SV>::a[l]) * (so[up + L::OU] - so[dn + L::OU]);
-                    sv += R(Coef<SV>::a[l]) * (so[up + L::OV] - so[dn + L::OV]);
+                    R uu, vu, ud, vd;
+                    plane_uv<R>(so, (ty + S + l) * HX + hx, uu, vu);
+                    plane_uv<R>(so, (ty + S - l) * HX + hx, ud, vd);
+                    su += R(Coef<SV>::a[l]) * (uu - ud);
+                    sv += R(Coef<SV>::a[l]) * (vu - vd);
                 }
                 gyl[0][ty][hx] = eyr * su;
                 gyl[1][ty][hx] = eyr * sv;
@@ -972,9 +1110,9 @@ __device__ __forceinline__ void march_split(SmemSplit<Halo<SC, SV>::S, TX, TY, R
                     sl = sl < 0 ? sl + Q : (sl >= Q ? sl - Q : sl);
                     return znode(sl);
                 };
-                if (mask & SX_CONV_X) stencil_dir<SC, SV, 0, true, false>(getx, dxi, dxi, R(0), acc, gd, dd);
-                if (mask & SX_CONV_Y) stencil_dir<SC, SV, 1, true, false>(gety, ey, ey, R(0), acc, gd, dd);
-                if (mask & SX_CONV_Z) stencil_dir<SC, SV, 2, true, false>(getz, dzi, dzi, R(0), acc, gd, dd);
+                if (mask & SX_CONV_X) stencil_dir<SC, SV, 0, true, false, KEEP>(getx, dxi, dxi, R(0), acc, gd, dd, &gas);
+                if (mask & SX_CONV_Y) stencil_dir<SC, SV, 1, true, false, KEEP>(gety, ey, ey, R(0), acc, gd, dd, &gas);
+                if (mask & SX_CONV_Z) stencil_dir<SC, SV, 2, true, false, KEEP>(getz, dzi, dzi, R(0), acc, gd, dd, &gas);
             }
             __syncthreads();                                   // 2: viscous part ready
             if (active) {
@@ -985,6 +1123,7 @@ __device__ __forceinline__ void march_split(SmemSplit<Halo<SC, SV>::S, TX, TY, R
                 for (int v = 0; v < NV; ++v) {
                     double r = double(acc[v] + xch[v][tid]);
                     if (f32 && v == 4) r += accE_shift;
+                    if (v == 1) fsum = __builtin_fma(fvol, r, fsum);
                     pend[v] = r;
                     if (UPD) {
                         double nv = __builtin_fma(sc.cg, r, wcur[v]);
@@ -1041,7 +1180,7 @@ __device__ __forceinline__ void march_split(SmemSplit<Halo<SC, SV>::S, TX, TY, R
         auto fetch_col = [&](double (&cq)[5], int k) {
             const unsigned bn = colbo + kbo(k);
 #pragma unroll
-            for (int v = 0; v < 5; ++v) cq[v] = active ? ldo(W + v * g.sv, bn) : (v == 0 ? 1.0 : 0.0);
+            for (int v = 0; v < 5; ++v) cq[v] = ldo(W + v * g.sv, bn);
         };
         auto stage_column = [&](int slot, const double (&cq)[5]) {
             double rho, u, v, w, T, p, H;
@@ -1069,7 +1208,7 @@ __device__ __forceinline__ void march_split(SmemSplit<Halo<SC, SV>::S, TX, TY, R
             stage_arrival(fa);
             stage_column(slot_new, cq);
             // viscosity of plane k from this thread's own ring record
-            R uc = 0, vc = 0, wc_ = 0, mu = 0, kcd = 0, smt = 0;
+            R uc = 0, vc = 0, wc_ = 0, mu = 0, kcd = 0, smt = 0, skt = 0;
             if (active && visc) {
                 const Node<R> Cz = znode(slot_k);
                 uc = Cz.u;
@@ -1077,8 +1216,15 @@ __device__ __forceinline__ void march_split(SmemSplit<Halo<SC, SV>::S, TX, TY, R
                 wc_ = Cz.w;
                 const R Tc = Cz.T;
                 mu = visc_pow<R>(Tc, gas) * R(gas.ire);
-                kcd = mu * R(gas.cp * gas.ipr);
                 smt = R(gas.s) * rcpr<R>(Tc);
+                if constexpr (THERMO) {   // k = mu c_p(T) / Pr, grad k = k (s/T + c_p'/c_p) grad T
+                    const double cpr = tp_cpR(gas, double(Tc));
+                    kcd = mu * R(gas.igM2 * cpr * gas.ipr);
+                    skt = smt + R(tp_dcpR(gas, double(Tc)) / cpr);
+                } else {
+                    kcd = mu * R(gas.cp * gas.ipr);
+                    skt = smt;
+                }
                 vmu[tid] = mu;
             }
             __syncthreads();                                   // 1: planes staged
@@ -1129,7 +1275,7 @@ __device__ __forceinline__ void march_split(SmemSplit<Halo<SC, SV>::S, TX, TY, R
                 acc[1] += N0;
                 acc[2] += N1;
                 acc[3] += N2;
-                acc[4] += uc * N0 + vc * N1 + wc_ * N2 + diss + (smt * kcd) * (Tx * Tx + Ty * Ty + Tz * Tz);
+                acc[4] += uc * N0 + vc * N1 + wc_ * N2 + diss + (skt * kcd) * (Tx * Tx + Ty * Ty + Tz * Tz);
             }
 #pragma unroll
             for (int v = 0; v < NV; ++v) xch[v][tid] = acc[v];
@@ -1138,6 +1284,7 @@ __device__ __forceinline__ void march_split(SmemSplit<Halo<SC, SV>::S, TX, TY, R
             slot_k = slot_k + 1 == Q ? 0 : slot_k + 1;
         }
     }
+    if (g.fpart) force_partial<2 * NR>(sm.fred, NR, fsum, g);
 }
 
 template <int S, int TX, int TY, typename R, bool SPLIT>
@@ -1149,7 +1296,7 @@ struct SmemOf<S, TX, TY, R, true> {
     using type = SmemSplit<S, TX, TY, R>;
 };
 
-template <int SC, int SV, int TX, int TY, int WPE, typename R, bool UPD, bool PIMG, bool SPLIT>
+template <int SC, int SV, int TX, int TY, int WPE, typename R, bool UPD, bool PIMG, bool SPLIT, int VAR = 0>
 __global__ void __attribute__((amdgpu_flat_work_group_size(TX * TY * (SPLIT ? 2 : 1), TX * TY * (SPLIT ? 2 : 1)),
                                amdgpu_waves_per_eu(WPE)))
 k_rhs_central(const double* __restrict__ W, double* __restrict__ out, double* __restrict__ Rp,
@@ -1158,11 +1305,11 @@ k_rhs_central(const double* __restrict__ W, double* __restrict__ out, double* __
     __shared__ typename SmemOf<Halo<SC, SV>::S, TX, TY, R, SPLIT>::type sm;
     const int k0 = blockIdx.z * kc;
     if constexpr (SPLIT)
-        march_split<SC, SV, TX, TY, R, UPD, PIMG>(sm, W, out, Rp, g, gas, sc, mask, blockIdx.x * TX,
-                                                  blockIdx.y * TY, k0, min(k0 + kc, g.nz));
+        march_split<SC, SV, TX, TY, R, UPD, PIMG, VAR>(sm, W, out, Rp, g, gas, sc, mask, blockIdx.x * TX,
+                                                       blockIdx.y * TY, k0, min(k0 + kc, g.nz));
     else
-        march<SC, SV, TX, TY, R, UPD, PIMG>(sm, W, out, Rp, g, gas, sc, mask, blockIdx.x * TX,
-                                            blockIdx.y * TY, k0, min(k0 + kc, g.nz));
+        march<SC, SV, TX, TY, R, UPD, PIMG, VAR>(sm, W, out, Rp, g, gas, sc, mask, blockIdx.x * TX,
+                                                 blockIdx.y * TY, k0, min(k0 + kc, g.nz));
 }
 
 // Persistent batched kernel: each workgroup pulls (box, column tile,
@@ -1242,10 +1389,72 @@ struct Tile {
     static constexpr int WPE = 2;
 };
 
+// Bulk forcing (the paper's force_rhs_1 sum reduction): f = -sum V R_rhou /
+// sum V from the fused launch's nwg partial sums (fixed order), stored
+// after them.
+__global__ void __launch_bounds__(256) k_force_final(KGrid g, int nwg)
+{
+    __shared__ double ra[256], rv[256];
+    double a = 0.0, v = 0.0;
+    for (int b = threadIdx.x; b < nwg; b += 256) a += g.fpart[b];
+    for (int j = threadIdx.x; j < g.ny; j += 256) v += g.y_eta[j];
+    ra[threadIdx.x] = a;
+    rv[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            ra[threadIdx.x] += ra[threadIdx.x + s];
+            rv[threadIdx.x] += rv[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) g.fpart[nwg] = -ra[0] / (rv[0] * (g.dx * g.nx) * (g.dz * g.nz));
+}
+
+// The force into a right-hand side (R, interior layout) or, after a fused
+// update, into the new state and the RK register: rho u += c f, rho E += c f u
+// with u of the state the right-hand side was evaluated on.
+__global__ void __launch_bounds__(256) k_force_apply(KGrid g, const double* __restrict__ W,
+                                                     double* __restrict__ out, double* __restrict__ Rp,
+                                                     int nwg, double cg, int upd, int write_prev)
+{
+    const double f = g.fpart[nwg];
+    const long long T = (long long)gridDim.x * 256;
+    for (long long m = (long long)blockIdx.x * 256 + threadIdx.x; m < g.nint; m += T) {
+        const int i = (int)(m % g.nx);
+        const long long jk = m / g.nx;
+        const int j = (int)(jk % g.ny);
+        const int k = (int)(jk / g.ny);
+        const long long n = g.base + (long long)k * g.sz + (long long)j * g.sy + i;
+        const double u = W[g.sv + n] / W[n];
+        if (upd) {
+            out[g.sv + n] += cg * f;
+            out[4 * g.sv + n] += cg * (f * u);
+            if (write_prev) {
+                Rp[g.nint + m] += f;
+                Rp[4 * g.nint + m] += f * u;
+            }
+        } else {
+            out[g.nint + m] += f;
+            out[4 * g.nint + m] += f * u;
+        }
+    }
+}
+
+static hipError_t launch_force(const KGrid& g, int nwg, const double* W, double* out, double* Rp,
+                               const StepCoef* step, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_force_final, dim3(1), dim3(256), 0, st, g, nwg);
+    const long long nb = min((g.nint + 255) / 256, (long long)4096);
+    hipLaunchKernelGGL(k_force_apply, dim3((unsigned)nb), dim3(256), 0, st, g, W, out, Rp, nwg,
+                       step ? step->cg : 0.0, step ? 1 : 0, step ? step->write_prev : 0);
+    return hipGetLastError();
+}
+
 template <int SC, int SV, typename R>
 static hipError_t launch_rhs_SR(const KGrid& g, const KGas& gas, const double* W, double* out,
                                 double* Rprev, const StepCoef* step, unsigned mask, bool pimg,
-                                hipStream_t st)
+                                hipStream_t st, int var)
 {
     constexpr int S = Halo<SC, SV>::S;
     constexpr int TX = Tile<R, S>::TX, TY = Tile<R, S>::TY, WPE = Tile<R, S>::WPE;
@@ -1275,6 +1484,45 @@ static hipError_t launch_rhs_SR(const KGrid& g, const KGas& gas, const double* W
     }
     const int kc = (g.nz + nch - 1) / nch;
     dim3 grid((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY, (g.nz + kc - 1) / kc);
+    const int nwg = (int)(grid.x * grid.y * grid.z);
+    // bulk forcing on a full right-hand side, after the fused launch
+    const bool force = g.fpart && (step || mask == (unsigned)SX_ALL);
+    if (var == 1) {
+        // KEEP-n flux: FP64, equal orders, no periodic images (checked at init)
+        if constexpr (SC == SV && std::is_same<R, double>::value && SP) {
+            if (pimg) return hipErrorInvalidValue;
+            StepCoef none{0.0, 0.0, 0, 0};
+            if (step)
+                hipLaunchKernelGGL((k_rhs_central<SC, SV, TX, TY, WPE, R, true, false, SP, 1>), grid, dim3(NTH),
+                                   0, st, W, out, Rprev, g, gas, *step, (unsigned)SX_ALL, kc);
+            else
+                hipLaunchKernelGGL((k_rhs_central<SC, SV, TX, TY, WPE, R, false, false, SP, 1>), grid,
+                                   dim3(NTH), 0, st, W, out, Rprev, g, gas, none, mask, kc);
+            hipError_t e = hipGetLastError();
+            if (e == hipSuccess && force) e = launch_force(g, nwg, W, out, Rprev, step, st);
+            return e;
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
+    if (var == 2) {
+        // thermally perfect gas: equal orders, no periodic images (checked at init)
+        if constexpr (SC == SV) {
+            if (pimg) return hipErrorInvalidValue;
+            StepCoef none{0.0, 0.0, 0, 0};
+            if (step)
+                hipLaunchKernelGGL((k_rhs_central<SC, SV, TX, TY, WPE, R, true, false, SP, 2>), grid, dim3(NTH),
+                                   0, st, W, out, Rprev, g, gas, *step, (unsigned)SX_ALL, kc);
+            else
+                hipLaunchKernelGGL((k_rhs_central<SC, SV, TX, TY, WPE, R, false, false, SP, 2>), grid,
+                                   dim3(NTH), 0, st, W, out, Rprev, g, gas, none, mask, kc);
+            hipError_t e = hipGetLastError();
+            if (e == hipSuccess && force) e = launch_force(g, nwg, W, out, Rprev, step, st);
+            return e;
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
     if (step && pimg) {
         // periodic images are written only by the equal-order kernels (the
         // handle never selects them for mixed orders)
@@ -1291,19 +1539,21 @@ static hipError_t launch_rhs_SR(const KGrid& g, const KGas& gas, const double* W
         hipLaunchKernelGGL((k_rhs_central<SC, SV, TX, TY, WPE, R, false, false, SP>), grid, dim3(NTH), 0,
                            st, W, out, Rprev, g, gas, none, mask, kc);
     }
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && force) e = launch_force(g, nwg, W, out, Rprev, step, st);
+    return e;
 }
 
 template <int SC, typename R>
 static hipError_t launch_rhs_CR(int Lv, const KGrid& g, const KGas& gas, const double* W, double* out,
                                 double* Rprev, const StepCoef* step, unsigned mask, bool pimg,
-                                hipStream_t st)
+                                hipStream_t st, int var)
 {
     switch (Lv) {
-    case 1: return launch_rhs_SR<SC, 1, R>(g, gas, W, out, Rprev, step, mask, pimg, st);
-    case 2: return launch_rhs_SR<SC, 2, R>(g, gas, W, out, Rprev, step, mask, pimg, st);
-    case 3: return launch_rhs_SR<SC, 3, R>(g, gas, W, out, Rprev, step, mask, pimg, st);
-    case 4: return launch_rhs_SR<SC, 4, R>(g, gas, W, out, Rprev, step, mask, pimg, st);
+    case 1: return launch_rhs_SR<SC, 1, R>(g, gas, W, out, Rprev, step, mask, pimg, st, var);
+    case 2: return launch_rhs_SR<SC, 2, R>(g, gas, W, out, Rprev, step, mask, pimg, st, var);
+    case 3: return launch_rhs_SR<SC, 3, R>(g, gas, W, out, Rprev, step, mask, pimg, st, var);
+    case 4: return launch_rhs_SR<SC, 4, R>(g, gas, W, out, Rprev, step, mask, pimg, st, var);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1313,11 +1563,12 @@ static hipError_t launch_rhs_R(const KGrid& g, const KGas& gas, const KScheme& s
                                double* out, double* Rprev, const StepCoef* step, unsigned mask,
                                bool pimg, hipStream_t st)
 {
+    const int var = sc.flux == SX_FLUX_KEEP ? 1 : (gas.thermo ? 2 : 0);
     switch (sc.L) {
-    case 1: return launch_rhs_CR<1, R>(sc.Lv, g, gas, W, out, Rprev, step, mask, pimg, st);
-    case 2: return launch_rhs_CR<2, R>(sc.Lv, g, gas, W, out, Rprev, step, mask, pimg, st);
-    case 3: return launch_rhs_CR<3, R>(sc.Lv, g, gas, W, out, Rprev, step, mask, pimg, st);
-    case 4: return launch_rhs_CR<4, R>(sc.Lv, g, gas, W, out, Rprev, step, mask, pimg, st);
+    case 1: return launch_rhs_CR<1, R>(sc.Lv, g, gas, W, out, Rprev, step, mask, pimg, st, var);
+    case 2: return launch_rhs_CR<2, R>(sc.Lv, g, gas, W, out, Rprev, step, mask, pimg, st, var);
+    case 3: return launch_rhs_CR<3, R>(sc.Lv, g, gas, W, out, Rprev, step, mask, pimg, st, var);
+    case 4: return launch_rhs_CR<4, R>(sc.Lv, g, gas, W, out, Rprev, step, mask, pimg, st, var);
     default: return hipErrorInvalidValue;
     }
 }

@@ -20,6 +20,7 @@ SX_BC_PERIODIC, SX_BC_WALL, SX_BC_EXTRAP, SX_BC_FROZEN = range(4)
 SX_Y_UNIFORM, SX_Y_TANH2, SX_Y_TANH1 = range(3)
 SX_CONV_X, SX_CONV_Y, SX_CONV_Z, SX_VISC, SX_ALL = 1, 2, 4, 8, 15
 SX_FP64, SX_FP32_FLUX = 0, 1
+SX_FLUX_SPLIT, SX_FLUX_KEEP = 0, 1
 
 
 class SxError(RuntimeError):
@@ -38,14 +39,17 @@ class sx_grid(ctypes.Structure):
 class sx_gas(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("mach", ctypes.c_double),
                 ("reynolds", ctypes.c_double), ("prandtl", ctypes.c_double),
-                ("visc_exp", ctypes.c_double), ("t_wall", ctypes.c_double)]
+                ("visc_exp", ctypes.c_double), ("t_wall", ctypes.c_double),
+                ("thermo", ctypes.c_int), ("nasa", ctypes.c_double * 5), ("t_ref", ctypes.c_double)]
 
 
 class sx_scheme(ctypes.Structure):
     _fields_ = [("central_order", ctypes.c_int), ("weno_order", ctypes.c_int),
                 ("visc_order", ctypes.c_int), ("sensor", ctypes.c_int),
                 ("sensor_thr", ctypes.c_double), ("sensor_eps", ctypes.c_double),
-                ("weno_eps", ctypes.c_double), ("precision", ctypes.c_int)]
+                ("weno_eps", ctypes.c_double), ("precision", ctypes.c_int),
+                ("central_flux", ctypes.c_int), ("keep_n", ctypes.c_int),
+                ("bulk_forcing", ctypes.c_int)]
 
 
 class sx_layout(ctypes.Structure):
@@ -132,9 +136,14 @@ def make_structs(case, precision: int = SX_FP64):
     g = sx_grid(case.nx, case.ny, case.nz, case.lx, case.ly, case.lz, case.y0, case.ymap,
                 case.beta)
     g.bc[:] = list(case.bc)
-    gas = sx_gas(case.gamma, case.mach, case.reynolds, case.prandtl, case.visc_exp, case.t_wall)
+    gas = sx_gas(case.gamma, case.mach, case.reynolds, case.prandtl, case.visc_exp, case.t_wall,
+                 getattr(case, "thermo", 0))
+    gas.nasa[:] = [float(x) for x in getattr(case, "nasa", (3.5, 0.0, 0.0, 0.0, 0.0))]
+    gas.t_ref = float(getattr(case, "t_ref", 300.0))
     sc = sx_scheme(case.central_order, case.weno_order, case.visc_order, case.sensor,
-                   case.sensor_thr, case.sensor_eps, case.weno_eps, precision)
+                   case.sensor_thr, case.sensor_eps, case.weno_eps, precision,
+                   getattr(case, "central_flux", 0), getattr(case, "keep_n", 0),
+                   getattr(case, "bulk_forcing", 0))
     return g, gas, sc
 
 

@@ -75,6 +75,20 @@ def _init(case, **patch):
     ({"lx": 0.0}, sx.SX_EINVAL),
     ({"ymap": 9}, sx.SX_EINVAL),
     ({"nx": 1024, "ny": 1024, "nz": 1024}, sx.SX_EINVAL),   # over 4 GiB per variable
+    ({"central_flux": 2}, sx.SX_EINVAL),
+    ({"central_flux": 1, "keep_n": 17}, sx.SX_EINVAL),
+    # KEEP-n is built for FP64, sensor off, equal convective and viscous orders
+    ({"central_flux": 1, "precision": sx.SX_FP32_FLUX}, sx.SX_EUNSUPPORTED),
+    ({"central_flux": 1, "sensor": 1}, sx.SX_EUNSUPPORTED),
+    ({"central_flux": 1, "visc_order": 4}, sx.SX_EUNSUPPORTED),
+    ({"bulk_forcing": 2}, sx.SX_EINVAL),
+    ({"thermo": 2}, sx.SX_EINVAL),
+    ({"thermo": 1, "t_ref": 0.0}, sx.SX_EINVAL),
+    # the thermally perfect gas is built for the central split form, equal orders
+    ({"thermo": 1, "sensor": 1}, sx.SX_EUNSUPPORTED),
+    ({"thermo": 1, "central_flux": 1}, sx.SX_EUNSUPPORTED),
+    ({"thermo": 1, "visc_order": 4}, sx.SX_EUNSUPPORTED),
+    ({"bulk_forcing": 1, "sensor": 1}, sx.SX_EUNSUPPORTED),
 ])
 def test_invalid_descriptions_rejected_without_device(patch, code):
     rc, h = _init(inputs.tgv_case(16), **patch)
@@ -112,6 +126,8 @@ def _init_batch(cases, **patch):
                 setattr(g, k, v)
             if hasattr(s, k):
                 setattr(s, k, v)
+            if hasattr(gas, k):
+                setattr(gas, k, v)
         grids[b], gases[b] = g, gas
         sc = sc or s
     h = ctypes.c_void_p()
@@ -131,8 +147,12 @@ def test_batch_rejections_without_device():
     ch = inputs.channel_case(32, 16, 8)
     assert _init_batch([ch])[0] == sx.SX_EUNSUPPORTED
     assert _init_batch(cases, central_order=5)[0] == sx.SX_EINVAL
-    # the persistent kernels take one order for convective and viscous terms
+    # the persistent kernels take one order for convective and viscous terms,
+    # the split-form flux and no bulk forcing
     assert _init_batch(cases, visc_order=4)[0] == sx.SX_EUNSUPPORTED
+    assert _init_batch(cases, central_flux=1)[0] == sx.SX_EUNSUPPORTED
+    assert _init_batch(cases, bulk_forcing=1)[0] == sx.SX_EUNSUPPORTED
+    assert _init_batch(cases, thermo=1)[0] == sx.SX_EUNSUPPORTED
     # blocks narrower than twice the ghost width cannot hold periodic images
     small = inputs.Case(**{**inputs.tgv_case(16).__dict__, "nz": 5})
     assert _init_batch([small])[0] == sx.SX_EUNSUPPORTED
