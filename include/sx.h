@@ -231,6 +231,25 @@ int sx_set_flag_override(sx_handle* h, const unsigned char* fx, const unsigned c
  * caller. Synchronises the stream. SX_ESTATE if the sensor is off. */
 int sx_get_flags(sx_handle* h, unsigned char* fx, unsigned char* fy, unsigned char* fz);
 
+/* For callers that cannot allocate device memory at call time (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the diagnostics of sx_diagnostics, written asynchronously on the bound
+ * stream into out, a caller-owned device array of 16 doubles in the field
+ * order of sx_diag (mass, momentum[3], energy, kinetic, max_mach, min_rho,
+ * min_p, nonfinite, nonphysical, residual_rhou, weno_fraction[3], volume).
+ * Same kernels and summation order as sx_diagnostics, so the values are
+ * bitwise equal; R as there. Nothing is allocated and nothing synchronises:
+ * the reduction partials, per-block result rows and flagged-face counters
+ * live in one fixed device array of the library (about 164 KB per GPU,
+ * allocated by the HIP runtime with the code object and held until the
+ * process ends). Every call on a GPU uses that GPU's array and overwrites
+ * what the previous call left there, so calls whose launches overlap on one
+ * GPU (different streams, or host threads) race. The status is not checked
+ * here: out[9] and out[10] count non-finite and non-physical nodes.
+ * SX_EINVAL for a batch handle of more than 256 blocks (the array holds 256
+ * result rows) or a null out; SX_ESTATE before sx_bind. */
+int sx_diagnostics_noalloc(sx_handle* h, const double* R, double* out);
+
 /* Kernel timing for measurement. When enabled, sx_rk3_step brackets every
  * launch of the fused right-hand-side/update kernel with HIP events recorded
  * on the bound stream. sx_timing_read synchronises the recorded events,

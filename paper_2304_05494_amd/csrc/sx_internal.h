@@ -164,6 +164,8 @@ void batch_tile_shape(const KScheme& sc, int variant, int* tx, int* ty);
 hipError_t launch_diagnostics(const KGrid& g, const KGas& gas, const KScheme& sc,
                               const double* W, const double* R, double* scratch,
                               int nscratch_blocks, hipStream_t st);
+hipError_t launch_diagnostics_rows(const KGrid& g, const KGas& gas, const double* W, const double* R,
+                                   double* part, int nblk, double* res, hipStream_t st);
 hipError_t launch_max_rate(const KGrid& g, const KGas& gas, const double* W, double* scratch,
                            int nscratch_blocks, hipStream_t st);
 // Buffers of the hybrid (sensor + WENO) path.

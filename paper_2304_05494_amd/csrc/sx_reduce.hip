@@ -170,6 +170,15 @@ hipError_t launch_diagnostics(const KGrid& g, const KGas& gas, const KScheme&, c
     return hipGetLastError();
 }
 
+// Partials in part[0 .. nblk*kDiagVals), the kDiagVals results in res.
+hipError_t launch_diagnostics_rows(const KGrid& g, const KGas& gas, const double* W, const double* R,
+                                   double* part, int nblk, double* res, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_diag_partial, dim3(nblk), dim3(RB), 0, st, g, gas, W, R, part);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(RB), 0, st, part, nblk, kDiagVals, 0, res);
+    return hipGetLastError();
+}
+
 // scratch: nblk partials followed by one result (largest CFL rate).
 hipError_t launch_max_rate(const KGrid& g, const KGas& gas, const double* W, double* scratch,
                            int nblk, hipStream_t st)
@@ -181,3 +190,133 @@ hipError_t launch_max_rate(const KGrid& g, const KGas& gas, const double* W, dou
 
 }  // namespace sx
 
+// ---- diagnostics without allocation ---------------------------------------
+// Scratch of the no-allocation diagnostics: the partial rows of the
+// reduction workgroups, one result row per block (up to kNoallocMaxBoxes
+// blocks of a batch) and the three flagged-face counters. One copy per
+// device, held until the process ends; every call on a device shares it.
+#include <mutex>
+
+#include "sx_handle.h"
+
+namespace {
+constexpr int kNoallocMaxBoxes = 256;
+constexpr long long kNoallocPart = (long long)sx::kReduceBlocks * sx::kDiagVals;
+constexpr long long kNoallocRows = kNoallocPart;                                   // result rows
+constexpr long long kNoallocCount = kNoallocRows + (long long)kNoallocMaxBoxes * sx::kDiagVals;  // counters
+constexpr long long kNoallocDoubles = kNoallocCount + 4;
+}  // namespace
+
+static __device__ __align__(256) double scratch[kNoallocDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current. The array's name in host code is only a
+// host-side stand-in; kernels get this address.
+hipError_t noalloc_scratch(double** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+// Single block: the result row, with the flagged-face fractions (sensor
+// on) formed from the counters exactly as the synchronising call does.
+__global__ void k_emit_single(const double* __restrict__ res, const unsigned long long* __restrict__ fc,
+                              int sensor, double nfx, double nfy, double nfz, double* __restrict__ out)
+{
+    const int q = threadIdx.x;
+    if (q >= sx::kDiagVals) return;
+    double v = res[q];
+    if (sensor) {
+        if (q == 12) v = (double)fc[0] / nfx;
+        if (q == 13) v = (double)fc[1] / nfy;
+        if (q == 14) v = (double)fc[2] / nfz;
+    }
+    out[q] = v;
+}
+
+// Batch: the per-block rows combined in block order with the rules of the
+// synchronising call (sums; largest Mach number; smallest density and
+// pressure; no flagged faces).
+__global__ void k_emit_batch(const double* __restrict__ rows, int nbox, double* __restrict__ out)
+{
+    if (threadIdx.x != 0) return;
+    double v[sx::kDiagVals];
+    for (int k = 0; k < sx::kDiagVals; ++k) v[k] = 0.0;
+    v[6] = -__builtin_huge_val();
+    v[7] = v[8] = __builtin_huge_val();
+    for (int b = 0; b < nbox; ++b) {
+        const double* a = rows + (long long)b * sx::kDiagVals;
+        for (int k = 0; k < sx::kDiagVals; ++k)
+            if (k <= 5 || k == 9 || k == 10 || k == 11 || k == 15) v[k] += a[k];
+        v[6] = fmax(v[6], a[6]);
+        v[7] = fmin(v[7], a[7]);
+        v[8] = fmin(v[8], a[8]);
+    }
+    for (int k = 0; k < sx::kDiagVals; ++k) out[k] = v[k];
+}
+
+}  // namespace
+
+extern "C" int sx_diagnostics_noalloc(sx_handle* h, const double* R, double* out)
+{
+    if (!h) return SX_EINVAL;
+    if (!out) return sx_fail(h, SX_EINVAL, "sx_diagnostics_noalloc: null output");
+    if (!h->bound) return sx_fail(h, SX_ESTATE, "sx_diagnostics_noalloc: no buffers bound");
+    if (h->batch && (int)h->boxes.size() > kNoallocMaxBoxes)
+        return sx_fail(h, SX_EINVAL, "sx_diagnostics_noalloc: more blocks than the no-allocation scratch "
+                                     "holds result rows for (256)");
+    double* s = nullptr;
+    hipError_t e = noalloc_scratch(&s);
+    if (e != hipSuccess) return sx_hip_fail(h, e, "sx_diagnostics_noalloc: scratch address");
+    const int nb = sx::kReduceBlocks, nv = sx::kDiagVals;
+    double* part = s;
+    double* rows = s + kNoallocRows;
+    unsigned long long* fc = reinterpret_cast<unsigned long long*>(s + kNoallocCount);
+    if (h->batch) {
+        for (size_t b = 0; b < h->boxes.size() && e == hipSuccess; ++b) {
+            const SxBox& x = h->boxes[b];
+            e = sx::launch_diagnostics_rows(x.kg, x.kgas, h->W[h->cur] + x.woff, R ? R + x.roff : nullptr,
+                                            part, nb, rows + (long long)b * nv, h->st);
+        }
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_emit_batch, dim3(1), dim3(64), 0, h->st, rows, (int)h->boxes.size(), out);
+            e = hipGetLastError();
+        }
+    } else {
+        e = sx::launch_diagnostics_rows(h->kg, h->kgas, h->W[h->cur], R, part, nb, rows, h->st);
+        if (e == hipSuccess && h->ks.sensor) {
+            double* Wc = h->W[h->cur];
+            e = sx::launch_ghost_fill(h->kg, h->kgas, Wc, h->st);
+            if (e == hipSuccess)
+                e = sx::launch_sensor_flags(h->kg, h->ks, Wc, h->wb, h->flag_override, h->st);
+            if (e == hipSuccess)
+                e = sx::launch_count_flags(h->kg, h->wb.f[0], h->wb.f[1], h->wb.f[2], fc, h->st);
+        }
+        if (e == hipSuccess) {
+            const sx_grid& g = h->grid;
+            hipLaunchKernelGGL(k_emit_single, dim3(1), dim3(64), 0, h->st, rows, fc, h->ks.sensor,
+                               (double)g.nz * g.ny * (g.nx + 1), (double)g.nz * (g.ny + 1) * g.nx,
+                               (double)(g.nz + 1) * g.ny * g.nx, out);
+            e = hipGetLastError();
+        }
+    }
+    if (e != hipSuccess) return sx_hip_fail(h, e, "sx_diagnostics_noalloc");
+    return SX_OK;
+}

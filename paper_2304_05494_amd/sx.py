@@ -81,7 +81,7 @@ class sx_tiling(ctypes.Structure):
 
 EXPORTS = ["sx_init", "sx_finalize", "sx_get_layout", "sx_bind", "sx_current", "sx_fill_ghosts",
            "sx_rhs", "sx_rk3_step", "sx_compute_dt", "sx_diagnostics", "sx_set_flag_override",
-           "sx_get_flags",
+           "sx_get_flags", "sx_diagnostics_noalloc",
            "sx_timing_enable", "sx_timing_read", "sx_init_batch", "sx_get_box", "sx_set_tiling",
            "sx_get_tiling", "sx_autotune", "sx_set_graph", "sx_last_error"]
 
@@ -113,6 +113,7 @@ def load() -> ctypes.CDLL:
     L.sx_diagnostics.argtypes = [H, dp, ctypes.POINTER(sx_diag)]
     L.sx_set_flag_override.argtypes = [H, dp, dp, dp]
     L.sx_get_flags.argtypes = [H, dp, dp, dp]
+    L.sx_diagnostics_noalloc.argtypes = [H, dp, dp]
     L.sx_timing_enable.argtypes = [H, ctypes.c_int]
     L.sx_timing_read.argtypes = [H, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double)]
     L.sx_init_batch.argtypes = [ctypes.c_int, ctypes.POINTER(sx_grid), ctypes.POINTER(sx_gas),
@@ -270,6 +271,12 @@ class Handle:
         out = [np.zeros((c.nz, c.ny, c.nx + 1), np.uint8), np.zeros((c.nz, c.ny + 1, c.nx), np.uint8),
                np.zeros((c.nz + 1, c.ny, c.nx), np.uint8)]
         self._check(self.lib.sx_get_flags(self.h, *[a.ctypes.data for a in out]))
+        return out
+
+    def sx_diagnostics_noalloc(self, out, R=None):
+        """Diagnostics into `out` (a float64 device tensor of 16 values),
+        asynchronously, using the library's fixed scratch array."""
+        self._check(self.lib.sx_diagnostics_noalloc(self.h, _ptr(R), _ptr(out)))
         return out
 
     def sx_timing_enable(self, enable: bool = True):
