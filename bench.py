@@ -527,7 +527,7 @@ def main():
     avg_launch_s = kern_ms / launches * 1e-3
     alg_bytes_launch = ALG_BYTES_PER_POINT_STEP / SUBSTEPS * case.points
     achieved = alg_bytes_launch / avg_launch_s / 1e9
-    kernel = "k_rhs_central<3, 32, 8, 2, double, true, false, true>"
+    kernel = "k_rhs_central<3, 3, 32, 8, 2, double, true, false, true, 0>"
     traffic = load_traffic(kernel)
     line = {
         "metric": "grid-point updates/s per RK3 step (FP64 vs FP32-flux) + % HBM roofline",
@@ -583,7 +583,7 @@ def main():
     W32 = h32.to_layout(Wn)
     h32.sx_bind(W32)
     ms32, l32 = time_steps(h32, dt, args.steps, args.warmup, args.reps)
-    fl32 = load_flops("k_rhs_central<3, 64, 8, 2, float, true, false, false>")
+    fl32 = load_flops("k_rhs_central<3, 3, 64, 8, 2, float, true, false, false, 0>")
     line["fp32_flux"] = {
         "valu_fp32_tflops": None if fl32 is None else fl32["fp32_flops_per_launch"] / (l32 * 1e-3) / 1e12,
         "value": case.points / (ms32 * 1e-3),

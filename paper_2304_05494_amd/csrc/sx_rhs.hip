@@ -22,10 +22,10 @@
 // Rprev.
 //
 // FP64 splits the work of a column between two waves (march_split): one
-// holds the convective terms, the mixed x-y viscous terms and the update,
-// the other the arrival plane, the column ring, the mixed-derivative queues
-// and the remaining viscous terms, and passes its part of the RHS through
-// LDS. Each wave then needs under 256
+// stages the output plane and the column ring and holds the convective
+// terms, the mixed x-y viscous terms and the update, the other the arrival
+// plane, the mixed-derivative queues and the remaining viscous terms, and
+// passes its part of the RHS through LDS. Each wave then needs under 256
 // registers, so every SIMD runs two waves whose instruction streams hide
 // each other's LDS and memory latencies (one wave of the unsplit FP64 march
 // needs ~390 registers and leaves the SIMD idle on every wait). FP32 halves
@@ -539,10 +539,12 @@ __device__ __forceinline__ void march(Smem<Halo<SC, SV>::S, TX, TY, R>& sm, cons
         const unsigned kb = kbo(k);
 #pragma unroll
         for (int a = 0; a < NPT; ++a) {
-            const unsigned bo = hbo[a] + kb;
+            if (a + 1 < NPT || tid + a * NT < HP) {   // the last round covers the tail of the plane
+                const unsigned bo = hbo[a] + kb;
 #pragma unroll
-            for (int v = 0; v < 5; ++v)
-                if (v < nvar) f.q[a][v] = ldo(W + v * g.sv, bo);
+                for (int v = 0; v < 5; ++v)
+                    if (v < nvar) f.q[a][v] = ldo(W + v * g.sv, bo);
+            }
         }
     };
     auto fetch_col = [&](double (&cq)[5], int k) {
@@ -864,12 +866,12 @@ struct SmemSplit {
 };
 
 // Role-split march: the workgroup holds two threads per tile column. Role 0
-// (the first TX*TY threads) stages the output plane, evaluates the
-// convective terms and the mixed x-y viscous terms and applies the update;
-// role 1 stages the arrival plane and the column ring, keeps the
+// (the first TX*TY threads) stages the output plane and the column ring,
+// evaluates the convective terms and the mixed x-y viscous terms and
+// applies the update; role 1 stages the arrival plane, keeps the
 // mixed-derivative queues, evaluates the viscosity before the plane barrier
-// (its own ring record is complete then) and the other viscous terms after
-// it, and passes them to role 0 through LDS. Each wave has one role, so the
+// (the ring record of plane k was staged S planes earlier) and the other
+// viscous terms after it, and passes them to role 0 through LDS. Each wave has one role, so the
 // two halves run as separate instruction streams that the SIMDs interleave,
 // and each holds half the per-column state. The work is divided so that
 // both roles reach the barriers at about the same time.
@@ -947,10 +949,12 @@ __device__ __forceinline__ void march_split(SmemSplit<Halo<SC, SV>::S, TX, TY, R
         const unsigned kb = kbo(k);
 #pragma unroll
         for (int a = 0; a < NPT; ++a) {
-            const unsigned bo = hbo[a] + kb;
+            if (a + 1 < NPT || tid + a * NR < HP) {   // the last round covers the tail of the plane
+                const unsigned bo = hbo[a] + kb;
 #pragma unroll
-            for (int v = 0; v < 5; ++v)
-                if (v < nvar) f.q[a][v] = ldo(W + v * g.sv, bo);
+                for (int v = 0; v < 5; ++v)
+                    if (v < nvar) f.q[a][v] = ldo(W + v * g.sv, bo);
+            }
         }
     };
     auto prims = [&](const double* w5, double& rho, double& u, double& v, double& w, double& T,
@@ -977,6 +981,17 @@ __device__ __forceinline__ void march_split(SmemSplit<Halo<SC, SV>::S, TX, TY, R
     // bulk forcing: cell volume of this column's nodes, running sum of V R_rhou (role 0)
     const double fvol = active && g.fpart ? g.dx * g.y_eta[j] * g.dz : 0.0;
     double fsum = 0.0;
+    // the column ring (z stencils of both roles) is staged by role 0
+    auto fetch_col = [&](double (&cq)[5], int k) {
+        const unsigned bn = colbo + kbo(k);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) cq[v] = ldo(W + v * g.sv, bn);
+    };
+    auto stage_column = [&](int slot, const double (&cq)[5]) {
+        double rho, u, v, w, T, p, H;
+        prims(cq, rho, u, v, w, T, p, H);
+        ring_write<R>(zring + L::ZREC * (slot * NR + tid), rho, u, v, w, T, p, H);
+    };
 
     if (role == 0) {
         // ---- convective terms, column ring, update ----------------------
@@ -1004,12 +1019,16 @@ __device__ __forceinline__ void march_split(SmemSplit<Halo<SC, SV>::S, TX, TY, R
             }
         };
         PlaneFetch<NPT> fo;
+        double cq[5];
         for (int t = 0; t < 2 * S; ++t) {
+            fetch_col(cq, k0 - S + t);
+            stage_column(t, cq);
             __syncthreads();
             __syncthreads();
         }
         fetch(fo, k0, 5);
         fetch_centre(k0);
+        fetch_col(cq, k0 + S);
 
         double pend[NV] = {0, 0, 0, 0, 0};
         double pend_w[NV] = {0, 0, 0, 0, 0};
@@ -1049,7 +1068,9 @@ __device__ __forceinline__ void march_split(SmemSplit<Halo<SC, SV>::S, TX, TY, R
         const R eyr = j < g.ny ? R(g.eta_y[j]) : R(0);
         int slot_k = S;
         for (int k = k0; k < k1; ++k) {
+            const int slot_new = slot_k + S >= Q ? slot_k + S - Q : slot_k + S;
             stage_output(fo);
+            stage_column(slot_new, cq);
             double wcur[5], rcur[5];
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
@@ -1061,6 +1082,7 @@ __device__ __forceinline__ void march_split(SmemSplit<Halo<SC, SV>::S, TX, TY, R
             if (k + 1 < k1) {
                 fetch(fo, k + 1, 5);
                 fetch_centre(k + 1);
+                fetch_col(cq, k + 1 + S);
             }
             sched_fence();
             R acc[NV] = {0, 0, 0, 0, 0};
@@ -1175,38 +1197,21 @@ __device__ __forceinline__ void march_split(SmemSplit<Halo<SC, SV>::S, TX, TY, R
                 m2[t] = m2[t + 1];
             }
         };
-        // the column ring (z stencils of both roles) is staged here, from
-        // the arrival plane's own column point
-        auto fetch_col = [&](double (&cq)[5], int k) {
-            const unsigned bn = colbo + kbo(k);
-#pragma unroll
-            for (int v = 0; v < 5; ++v) cq[v] = ldo(W + v * g.sv, bn);
-        };
-        auto stage_column = [&](int slot, const double (&cq)[5]) {
-            double rho, u, v, w, T, p, H;
-            prims(cq, rho, u, v, w, T, p, H);
-            ring_write<R>(zring + L::ZREC * (slot * NR + tid), rho, u, v, w, T, p, H);
-        };
         PlaneFetch<NPT> fa;
-        double cq[5];
         for (int t = 0; t < 2 * S; ++t) {
             fetch(fa, k0 - S + t, 4);
-            fetch_col(cq, k0 - S + t);
             stage_arrival(fa);
-            stage_column(t, cq);
             __syncthreads();
             arrive();
             shift();
             __syncthreads();
         }
         fetch(fa, k0 + S, 4);
-        fetch_col(cq, k0 + S);
 
         int slot_k = S;
         for (int k = k0; k < k1; ++k) {
             const int slot_new = slot_k + S >= Q ? slot_k + S - Q : slot_k + S;
             stage_arrival(fa);
-            stage_column(slot_new, cq);
             // viscosity of plane k from this thread's own ring record
             R uc = 0, vc = 0, wc_ = 0, mu = 0, kcd = 0, smt = 0, skt = 0;
             if (active && visc) {
@@ -1229,10 +1234,7 @@ __device__ __forceinline__ void march_split(SmemSplit<Halo<SC, SV>::S, TX, TY, R
             }
             __syncthreads();                                   // 1: planes staged
             arrive();
-            if (k + 1 < k1) {
-                fetch(fa, k + 1 + S, 4);
-                fetch_col(cq, k + 1 + S);
-            }
+            if (k + 1 < k1) fetch(fa, k + 1 + S, 4);
             sched_fence();
             R acc[NV] = {0, 0, 0, 0, 0};
             if (active && visc) {
