@@ -21,15 +21,23 @@
 // traffic of a substep is one read of W and Rprev, one write of W' and
 // Rprev.
 //
-// FP64 splits the work of a column between two waves (march_split): one
-// stages the output plane and the column ring and holds the convective
-// terms, the mixed x-y viscous terms and the update, the other the arrival
-// plane, the mixed-derivative queues and the remaining viscous terms, and
-// passes its part of the RHS through LDS. Each wave then needs under 256
+// FP64 splits the work of a column between two waves: one holds the
+// convective terms, the mixed x-y viscous terms and the update, the other
+// the mixed-derivative queues and the remaining viscous terms, and passes
+// its part of the RHS through LDS. Each wave then needs under 256
 // registers, so every SIMD runs two waves whose instruction streams hide
 // each other's LDS and memory latencies (one wave of the unsplit FP64 march
 // needs ~390 registers and leaves the SIMD idle on every wait). FP32 halves
 // the registers and keeps the unsplit march at two waves per SIMD.
+//
+// Single-block FP64 launches run the plane-ring march (march_ring): each
+// plane is fetched from HBM once, with its halo, by both waves together,
+// and kept in LDS as primitive records while it serves as arrival plane,
+// z-neighbour and output plane, its interior columns then moving to a ring
+// of past planes. The batched kernel, whose tiles do not all fit that
+// working set, runs march_split, which stages the arrival plane, the output
+// plane and the column ring separately; both derive the same values in the
+// same order, so a block gives the same bits either way.
 //
 // Precision forms: R = double (FP64 path) or R = float (FP32-flux form:
 // primitives are computed in FP64 and converted once per node, pressure
@@ -168,12 +176,14 @@ struct Node {
     R r, u, v, w, T, p, H;
 };
 
-// LDS record layouts. FP64: plane records of 6 doubles read as three 128-bit
-// loads, ordered (u, v | w, T | rho, p) so the viscous terms, which need u,
-// v, w, T only, read the first two; the enthalpy in a separate array. Ring
-// records (u, v | w, T | rho, H), p derived. (The 48-byte stride is bank
-// conflict free.) FP32: 7-float records (rho, u, v, w, T, p', H') read as
-// 32-bit loads (stride 7 is coprime with the 64 banks).
+// LDS record layouts. FP64: plane and ring records of 6 doubles read as
+// three 128-bit loads, ordered (u, v | w, T | rho, H) so the viscous terms,
+// which need u, v, w, T only, read the first two; the pressure is derived on
+// read, p = rho T / (gamma M^2), the same way on every FP64 path, so that
+// single-block and batched launches agree bitwise. (The 48-byte stride is
+// bank conflict free for 128-bit accesses.) FP32: 7-float records (rho, u,
+// v, w, T, p', H') read as 32-bit loads (stride 7 is coprime with the 64
+// banks).
 template <typename R>
 struct Layout;
 template <>
@@ -181,14 +191,12 @@ struct Layout<double> {
     static constexpr int PREC = 6;   // plane record
     static constexpr int ZREC = 6;   // ring record
     static constexpr int OU = 0, OV = 1;   // offsets of u and v in a plane record
-    static constexpr bool SEP_H = true;
 };
 template <>
 struct Layout<float> {
     static constexpr int PREC = 7;
     static constexpr int ZREC = 7;
     static constexpr int OU = 1, OV = 2;
-    static constexpr bool SEP_H = false;
 };
 
 // 16-byte vector of two doubles with its natural alignment, so that LDS
@@ -198,15 +206,15 @@ struct Layout<float> {
 typedef double dbl2 __attribute__((ext_vector_type(2)));
 
 template <typename R>
-__device__ __forceinline__ void plane_write(R* so, R* sH, int q, double rho, double u, double v,
+__device__ __forceinline__ void plane_write(R* so, int q, double rho, double u, double v,
                                             double w, double T, double p, double H)
 {
     if constexpr (std::is_same<R, double>::value) {
         dbl2* rec = reinterpret_cast<dbl2*>(so + 6 * q);
         rec[0] = dbl2{u, v};
         rec[1] = dbl2{w, T};
-        rec[2] = dbl2{rho, p};
-        sH[q] = H;
+        rec[2] = dbl2{rho, H};
+        (void)p;
     } else {
         R* rec = so + 7 * q;
         rec[0] = R(rho); rec[1] = R(u); rec[2] = R(v); rec[3] = R(w);
@@ -215,12 +223,12 @@ __device__ __forceinline__ void plane_write(R* so, R* sH, int q, double rho, dou
 }
 
 template <typename R>
-__device__ __forceinline__ Node<R> plane_read(const R* so, const R* sH, int q)
+__device__ __forceinline__ Node<R> plane_read(const R* so, int q, R igM2)
 {
     if constexpr (std::is_same<R, double>::value) {
         const dbl2* rec = reinterpret_cast<const dbl2*>(so + 6 * q);
         const dbl2 a = rec[0], b = rec[1], e = rec[2];
-        return Node<double>{e.x, a.x, a.y, b.x, b.y, e.y, sH[q]};
+        return Node<double>{e.x, a.x, a.y, b.x, b.y, e.x * b.y * igM2, e.y};
     } else {
         const R* rec = so + 7 * q;
         return Node<R>{rec[0], rec[1], rec[2], rec[3], rec[4], rec[5], rec[6]};
@@ -432,7 +440,6 @@ struct Smem {
     static constexpr int Q = 2 * S + 1;
     R sa[3][HP];                                                    // arrival plane: u, v, w
     __attribute__((aligned(16))) R so[Layout<R>::PREC * HP];        // output plane records
-    R sH[Layout<R>::SEP_H ? HP : 1];                                // output plane enthalpy
     R gyl[2][TY][HX];                                               // D_y u, D_y v of plane k
     __attribute__((aligned(16))) R zring[Q * NT * Layout<R>::ZREC]; // column records
     double fred[NT];                                                // bulk-forcing partial sums
@@ -488,7 +495,6 @@ __device__ __forceinline__ void march(Smem<Halo<SC, SV>::S, TX, TY, R>& sm, cons
     constexpr int Q = 2 * S + 1;
     auto& sa = sm.sa;
     R* const so = sm.so;
-    R* const sH = sm.sH;
     auto& gyl = sm.gyl;
     R* const zring = sm.zring;
     (void)HY;
@@ -603,7 +609,7 @@ __device__ __forceinline__ void march(Smem<Halo<SC, SV>::S, TX, TY, R>& sm, cons
             if (q < HP) {
                 double rho, u, v, w, T, p, H;
                 prims(f.q[a], rho, u, v, w, T, p, H);
-                plane_write<R>(so, sH, q, rho, u, v, w, T, p, H);
+                plane_write<R>(so, q, rho, u, v, w, T, p, H);
             }
         }
     };
@@ -761,8 +767,8 @@ __device__ __forceinline__ void march(Smem<Halo<SC, SV>::S, TX, TY, R>& sm, cons
                 }
             }
             R gx[4] = {0, 0, 0, 0}, gy[4] = {0, 0, 0, 0}, gz[4] = {0, 0, 0, 0}, dd[4];
-            auto getx = [&](int t) { return plane_read<R>(so, sH, c + t); };
-            auto gety = [&](int t) { return plane_read<R>(so, sH, c + t * HX); };
+            auto getx = [&](int t) { return plane_read<R>(so, c + t, igM2); };
+            auto gety = [&](int t) { return plane_read<R>(so, c + t * HX, igM2); };
             auto getz = [&](int t) {
                 int sl = slot_k + t;
                 sl = sl < 0 ? sl + Q : (sl >= Q ? sl - Q : sl);
@@ -857,7 +863,6 @@ struct SmemSplit {
     static constexpr int Q = 2 * S + 1;
     R sa[3][HP];                                                    // arrival plane: u, v, w
     __attribute__((aligned(16))) R so[Layout<R>::PREC * HP];        // output plane records
-    R sH[Layout<R>::SEP_H ? HP : 1];                                // output plane enthalpy
     R gyl[2][TY][HX];                                               // D_y u, D_y v of plane k
     __attribute__((aligned(16))) R zring[Q * NR * Layout<R>::ZREC]; // column records
     R xch[NV][NR];                                                  // viscous RHS of plane k
@@ -901,7 +906,6 @@ __device__ __forceinline__ void march_split(SmemSplit<Halo<SC, SV>::S, TX, TY, R
     static_assert(64 % TX == 0, "every row of the tile lies in one wave");
     auto& sa = sm.sa;
     R* const so = sm.so;
-    R* const sH = sm.sH;
     auto& gyl = sm.gyl;
     R* const zring = sm.zring;
     auto& xch = sm.xch;
@@ -976,8 +980,8 @@ __device__ __forceinline__ void march_split(SmemSplit<Halo<SC, SV>::S, TX, TY, R
         p = pr - pref;
     };
     auto znode = [&](int slot) { return ring_read<R>(zring + L::ZREC * (slot * NR + tid), igM2); };
-    auto getx = [&](int t) { return plane_read<R>(so, sH, c + t); };
-    auto gety = [&](int t) { return plane_read<R>(so, sH, c + t * HX); };
+    auto getx = [&](int t) { return plane_read<R>(so, c + t, igM2); };
+    auto gety = [&](int t) { return plane_read<R>(so, c + t * HX, igM2); };
     // bulk forcing: cell volume of this column's nodes, running sum of V R_rhou (role 0)
     const double fvol = active && g.fpart ? g.dx * g.y_eta[j] * g.dz : 0.0;
     double fsum = 0.0;
@@ -1014,7 +1018,7 @@ __device__ __forceinline__ void march_split(SmemSplit<Halo<SC, SV>::S, TX, TY, R
                 if (q < HP) {
                     double rho, u, v, w, T, p, H;
                     prims(f.q[a], rho, u, v, w, T, p, H);
-                    plane_write<R>(so, sH, q, rho, u, v, w, T, p, H);
+                    plane_write<R>(so, q, rho, u, v, w, T, p, H);
                 }
             }
         };
@@ -1289,6 +1293,428 @@ __device__ __forceinline__ void march_split(SmemSplit<Halo<SC, SV>::S, TX, TY, R
     if (g.fpart) force_partial<2 * NR>(sm.fred, NR, fsum, g);
 }
 
+// LDS working set of the plane-ring march (FP64): the halo planes k..k+S
+// (records (u, v | w, T | rho, H), pressure p = rho T / (gamma M^2)), the
+// interior columns of the past planes k-S..k-1 in the same records, and the
+// split march's D_y rows, hand-over and reduction arrays.
+template <int S, int TX, int TY>
+struct SmemRing {
+    static constexpr int NR = TX * TY;
+    static constexpr int HX = TX + 2 * S, HY = TY + 2 * S, HP = HX * HY;
+    __attribute__((aligned(16))) double halo[(S + 1) * HP * 6];   // planes k .. k+S
+    __attribute__((aligned(16))) double past[S * NR * 6];         // planes k-S .. k-1, interior columns
+    double gyl[2][TY][HX];                                          // D_y u, D_y v of plane k
+    double xch[NV][NR];                                             // viscous RHS of plane k
+    double vmu[NR];                                                 // viscosity of plane k (role 1 -> 0)
+    double fred[NR];                                                // bulk-forcing partial sums
+};
+
+// Plane-ring march (FP64, two roles as in march_split). Every plane of the
+// march is fetched from global memory once, with its x/y halo, by all the
+// workgroup's threads, and staged as primitive records into one of S+1
+// halo slots; it serves as the arrival plane k+S (mixed-derivative queues),
+// then as a z-neighbour, then as the output plane k (x and y stencils), and
+// when its slot is reused S+1 planes later its interior columns move to the
+// past ring, which serves the z stencils of planes k-S..k-1. The thread
+// staging a point of plane k+S first copies that point's record of plane
+// k-1 (the slot's previous plane) to the past ring, so no extra barrier is
+// needed. Besides the plane, role 0 fetches the centre state and the RK
+// register of the next output node.
+//
+// Per plane: (A) stage plane k+S (all threads), role 0 stores plane k-1 and
+// role 1 evaluates the viscosity of plane k from its column record; barrier
+// 1; (B) both roles issue the loads of plane k+S+1, role 1 forms the
+// in-plane derivatives of plane k+S and the viscous terms, role 0 the
+// convective and mixed x-y terms; barrier 2 (viscous hand-over); role 0
+// completes the update. Every slot written in (A) of plane k+1 (halo slot of
+// plane k, past slot of plane k-S) was last read before barrier 2 of plane
+// k.
+template <int SC, int SV, int TX, int TY, bool UPD, bool PIMG, int VAR = 0>
+__device__ __forceinline__ void march_ring(SmemRing<Halo<SC, SV>::S, TX, TY>& sm, const double* __restrict__ W,
+                                           double* __restrict__ out, double* __restrict__ Rp,
+                                           const KGrid& g, const KGas& gas, const StepCoef& sc,
+                                           unsigned mask_in, int i0, int j0, int k0, int k1)
+{
+    using R = double;
+    const unsigned mask = UPD ? (unsigned)SX_ALL : mask_in;
+    constexpr int S = Halo<SC, SV>::S;
+    constexpr bool KEEP = VAR == 1, THERMO = VAR == 2;
+    constexpr int NR = TX * TY;
+    constexpr int HX = TX + 2 * S, HP = HX * (TY + 2 * S);
+    constexpr int NPT = (HP + 2 * NR - 1) / (2 * NR);   // staged points per thread (both roles)
+    constexpr int Q = 2 * S + 1;
+    constexpr int NH = S + 1;                           // halo slots
+    static_assert(NR % 64 == 0, "each role fills whole waves");
+    static_assert(64 % TX == 0, "every row of the tile lies in one wave");
+    double* const halo = sm.halo;
+    double* const past = sm.past;
+    auto& gyl = sm.gyl;
+    auto& xch = sm.xch;
+    auto& vmu = sm.vmu;
+
+    const int role = threadIdx.x / NR;
+    const int tid = threadIdx.x - role * NR;
+    const int tx = tid % TX, ty = tid / TX;
+    const int i = i0 + tx, j = j0 + ty;
+    const bool active = i < g.nx && j < g.ny;
+    const int c = (ty + S) * HX + (tx + S);   // this column in a halo plane
+    const R ey = active ? R(g.eta_y[j]) : R(0);
+    const R eyy = active ? R(g.eta_yy[j]) : R(0);
+    const R dxi = R(g.dxi), dzi = R(g.dzi);
+    const R igM2 = R(gas.igM2);
+    const bool visc = mask & SX_VISC;
+
+    // global addressing as in march_split (uniform base + 32-bit offsets)
+    const int ic = min(i, g.nx - 1), jc = min(j, g.ny - 1);
+    const unsigned colbo = (unsigned)((g.base + (long long)jc * g.sy + ic) * 8);
+    const unsigned jibo = (unsigned)(((long long)jc * g.nx + ic) * 8);
+    auto kbo = [&](int k) { return (unsigned)((long long)k * g.sz * 8); };
+    auto kbr = [&](int k) { return (unsigned)((long long)k * g.ny * g.nx * 8); };
+    // the points this thread stages: q = threadIdx.x + a * 2 NR; halo points
+    // outside the ghosted block load the nearest ghosted node
+    unsigned hbo[NPT];
+    int hcol[NPT];   // past-ring column of an interior point, -1 otherwise
+#pragma unroll
+    for (int a = 0; a < NPT; ++a) {
+        const int q = threadIdx.x + a * 2 * NR;
+        const int hx = q % HX, hy = q / HX;
+        const int gi = min(max(i0 - S + hx, -g.ng), g.nx + g.ng - 1);
+        const int gj = min(max(j0 - S + hy, -g.ng), g.ny + g.ng - 1);
+        hbo[a] = (unsigned)((g.base + (long long)gj * g.sy + gi) * 8);
+        const bool in = q < HP && hx >= S && hx < S + TX && hy >= S && hy < S + TY;
+        hcol[a] = in ? (hy - S) * TX + (hx - S) : -1;
+    }
+    auto fetch = [&](PlaneFetch<NPT>& f, int k) {
+        const unsigned kb = kbo(k);
+#pragma unroll
+        for (int a = 0; a < NPT; ++a) {
+            if (a + 1 < NPT || (int)threadIdx.x + a * 2 * NR < HP) {
+                const unsigned bo = hbo[a] + kb;
+#pragma unroll
+                for (int v = 0; v < 5; ++v) f.q[a][v] = ldo(W + v * g.sv, bo);
+            }
+        }
+    };
+    auto prims = [&](const double* w5, double& rho, double& u, double& v, double& w, double& T, double& H) {
+        rho = w5[0];
+        const double ri = rcp(rho);
+        u = w5[1] * ri;
+        v = w5[2] * ri;
+        w = w5[3] * ri;
+        double pr;
+        if constexpr (THERMO) {   // thermally perfect: T from the internal energy
+            T = tp_T_of_e(gas, w5[4] * ri - 0.5 * (u * u + v * v + w * w));
+            pr = rho * T * gas.igM2;
+        } else {
+            pr = gas.gm1 * (w5[4] - 0.5 * rho * (u * u + v * v + w * w));
+            T = gas.gM2 * pr * ri;
+        }
+        H = (w5[4] + pr) * ri;
+    };
+    // stage plane p (fetched in f) into its halo slot; interior points first
+    // move the slot's previous plane p-S-1 to the past ring
+    auto stage = [&](const PlaneFetch<NPT>& f, int p) {
+        const int hs = ((p % NH) + NH) % NH;
+        const int ps = (((p - NH) % S) + S) % S;
+#pragma unroll
+        for (int a = 0; a < NPT; ++a) {
+            const int q = threadIdx.x + a * 2 * NR;
+            if (q < HP) {
+                double* rec = halo + 6 * (hs * HP + q);
+                if (hcol[a] >= 0) {
+                    const dbl2* o = reinterpret_cast<const dbl2*>(rec);
+                    const dbl2 o0 = o[0], o1 = o[1], o2 = o[2];
+                    dbl2* d = reinterpret_cast<dbl2*>(past + 6 * (ps * NR + hcol[a]));
+                    d[0] = o0;
+                    d[1] = o1;
+                    d[2] = o2;
+                }
+                double rho, u, v, w, T, H;
+                prims(f.q[a], rho, u, v, w, T, H);
+                ring_write<R>(rec, rho, u, v, w, T, 0.0, H);
+            }
+        }
+    };
+    // plane p = k + t of this column (t in -S..S) at output plane k
+    auto znode_at = [&](int k, int t) {
+        const int p = k + t;
+        if (t < 0) return ring_read<R>(past + 6 * ((((p % S) + S) % S) * NR + tid), igM2);
+        return ring_read<R>(halo + 6 * ((((p % NH) + NH) % NH) * HP + c), igM2);
+    };
+    // bulk forcing: cell volume of this column's nodes, running sum of V R_rhou (role 0)
+    const double fvol = active && g.fpart ? g.dx * g.y_eta[j] * g.dz : 0.0;
+    double fsum = 0.0;
+
+    PlaneFetch<NPT> fb;
+    // prologue: planes k0-S .. k0+S-1 staged; role 1 forms their in-plane
+    // derivatives (queue entries of planes k0-S .. k0+S-1)
+    R m0[Q], m1[Q], m2[Q];   // role 1: D_x w, D_y w, D_x u + D_y v of this column
+#pragma unroll
+    for (int t = 0; t < Q; ++t) m0[t] = m1[t] = m2[t] = R(0);
+    auto arrive = [&](int p) {
+        if (!active) return;
+        const double* hp = halo + 6 * ((((p % NH) + NH) % NH) * HP);
+        constexpr int QV = 2 * SV + 1;
+        R xw[QV], yw[QV], xu[QV], yv[QV];
+#pragma unroll
+        for (int t = 0; t < QV; ++t) {
+            const dbl2* rx = reinterpret_cast<const dbl2*>(hp + 6 * (c + t - SV));
+            const dbl2* ry = reinterpret_cast<const dbl2*>(hp + 6 * (c + (t - SV) * HX));
+            const dbl2 ax = rx[0], bx = rx[1], ay = ry[0], by = ry[1];
+            xu[t] = ax.x;
+            xw[t] = bx.x;
+            yv[t] = ay.y;
+            yw[t] = by.x;
+        }
+        m0[Q - 1] = dxi * d1<SV>(xw);
+        m1[Q - 1] = ey * d1<SV>(yw);
+        m2[Q - 1] = dxi * d1<SV>(xu) + ey * d1<SV>(yv);
+    };
+    auto shift = [&]() {
+#pragma unroll
+        for (int t = 0; t < Q - 1; ++t) {
+            m0[t] = m0[t + 1];
+            m1[t] = m1[t + 1];
+            m2[t] = m2[t + 1];
+        }
+    };
+    for (int t = 0; t < 2 * S; ++t) {
+        fetch(fb, k0 - S + t);
+        stage(fb, k0 - S + t);
+        __syncthreads();
+        if (role == 1) {
+            arrive(k0 - S + t);
+            shift();
+        }
+        __syncthreads();
+    }
+    fetch(fb, k0 + S);
+
+    auto getx = [&](int k, int t) { return ring_read<R>(halo + 6 * ((k % NH) * HP + c + t), igM2); };
+    auto gety = [&](int k, int t) { return ring_read<R>(halo + 6 * ((k % NH) * HP + c + t * HX), igM2); };
+
+    if (role == 0) {
+        // ---- convective terms, mixed x-y terms, update ------------------
+        double wc[5] = {}, rp[5] = {};
+        auto fetch_centre = [&](int k) {
+            const unsigned bn = colbo + kbo(k), bm = jibo + kbr(k);
+            if (UPD) {
+#pragma unroll
+                for (int v = 0; v < 5; ++v) wc[v] = ldo(W + v * g.sv, bn);
+                if (sc.read_prev) {
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) rp[v] = ldo(Rp + v * g.nint, bm);
+                }
+            }
+        };
+        fetch_centre(k0);
+        double pend[NV] = {0, 0, 0, 0, 0};
+        double pend_w[NV] = {0, 0, 0, 0, 0};
+        int pend_k = -1;   // plane of the pending stores, -1: none
+        auto flush = [&]() {
+            if (pend_k < 0) return;
+            if (UPD) {
+                const unsigned bn = colbo + kbo(pend_k);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) sto(out + v * g.sv, bn, pend_w[v]);
+                if constexpr (PIMG) {
+                    const int kk = pend_k;
+                    const int ox = i < g.ng ? g.nx : (i >= g.nx - g.ng ? -g.nx : 0);
+                    const int oy = j < g.ng ? g.ny : (j >= g.ny - g.ng ? -g.ny : 0);
+                    const int oz = kk < g.ng ? g.nz : (kk >= g.nz - g.ng ? -g.nz : 0);
+                    for (int c3 = 1; c3 < 8; ++c3) {
+                        const int dx = (c3 & 1) ? ox : 0, dy = (c3 & 2) ? oy : 0, dz = (c3 & 4) ? oz : 0;
+                        if (((c3 & 1) && !ox) || ((c3 & 2) && !oy) || ((c3 & 4) && !oz)) continue;
+                        const unsigned be = bn + (unsigned)((dx + (long long)dy * g.sy + (long long)dz * g.sz) * 8);
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) sto(out + v * g.sv, be, pend_w[v]);
+                    }
+                }
+                if (sc.write_prev) {
+                    const unsigned bm = jibo + kbr(pend_k);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) sto(Rp + v * g.nint, bm, pend[v]);
+                }
+            } else {
+                const unsigned bm = jibo + kbr(pend_k);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) sto(out + v * g.nint, bm, pend[v]);
+            }
+            pend_k = -1;
+        };
+
+        const R eyr = j < g.ny ? R(g.eta_y[j]) : R(0);
+        for (int k = k0; k < k1; ++k) {
+            stage(fb, k + S);
+            double wcur[5], rcur[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                wcur[v] = wc[v];
+                rcur[v] = rp[v];
+            }
+            flush();
+            __syncthreads();                                   // 1: plane k+S staged
+            if (k + 1 < k1) {
+                fetch(fb, k + 1 + S);
+                fetch_centre(k + 1);
+            }
+            sched_fence();
+            const int hk = k % NH;
+            const double* so = halo + 6 * (hk * HP);
+            R acc[NV] = {0, 0, 0, 0, 0};
+            // D_y u, D_y v over the x-extended columns of this thread's row;
+            // only this wave reads them (wavefront-scope ordering)
+            auto gy_at = [&](int hx) {
+                R su = 0, sv = 0;
+#pragma unroll
+                for (int l = 1; l <= SV; ++l) {
+                    R uu, vu, ud, vd;
+                    plane_uv<R>(so, (ty + S + l) * HX + hx, uu, vu);
+                    plane_uv<R>(so, (ty + S - l) * HX + hx, ud, vd);
+                    su += R(Coef<SV>::a[l]) * (uu - ud);
+                    sv += R(Coef<SV>::a[l]) * (vu - vd);
+                }
+                gyl[0][ty][hx] = eyr * su;
+                gyl[1][ty][hx] = eyr * sv;
+            };
+            if (visc && j < g.ny) {
+                gy_at(tx + S);
+                if (tx < 2 * S) gy_at(tx < S ? tx : TX + tx);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            auto gx_ = [&](int t) { return getx(k, t); };
+            auto gy_ = [&](int t) { return gety(k, t); };
+            if (active && visc) {
+                // mixed x-y parts of mu/3 d_i(div u)
+                R gyu[Q], gyv[Q];
+#pragma unroll
+                for (int t = 0; t < Q; ++t) {
+                    gyu[t] = gyl[0][ty][tx + t];
+                    gyv[t] = gyl[1][ty][tx + t];
+                }
+                const Node<R> Cc = gx_(0);
+                const R m3 = vmu[tid] * R(1.0 / 3.0);
+                const R mxy = m3 * (dxi * d1c<SV, S>(gyv));
+                const R myx = m3 * (dxi * d1c<SV, S>(gyu));
+                acc[1] += mxy;
+                acc[2] += myx;
+                acc[4] += Cc.u * mxy + Cc.v * myx;
+            }
+            if (active) {
+                R gd[4], dd[4];
+                auto gz_ = [&](int t) { return znode_at(k, t); };
+                if (mask & SX_CONV_X) stencil_dir<SC, SV, 0, true, false, KEEP>(gx_, dxi, dxi, R(0), acc, gd, dd, &gas);
+                if (mask & SX_CONV_Y) stencil_dir<SC, SV, 1, true, false, KEEP>(gy_, ey, ey, R(0), acc, gd, dd, &gas);
+                if (mask & SX_CONV_Z) stencil_dir<SC, SV, 2, true, false, KEEP>(gz_, dzi, dzi, R(0), acc, gd, dd, &gas);
+            }
+            __syncthreads();                                   // 2: viscous part ready
+            if (active) {
+                pend_k = k;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    const double r = acc[v] + xch[v][tid];
+                    if (v == 1) fsum = __builtin_fma(fvol, r, fsum);
+                    pend[v] = r;
+                    if (UPD) {
+                        double nv = __builtin_fma(sc.cg, r, wcur[v]);
+                        if (sc.read_prev) nv = __builtin_fma(sc.cz, rcur[v], nv);
+                        pend_w[v] = nv;
+                    }
+                }
+            }
+        }
+        flush();
+    } else {
+        // ---- in-plane derivative queues, viscous terms -------------------
+        for (int k = k0; k < k1; ++k) {
+            stage(fb, k + S);
+            // viscosity of plane k from this column's record
+            R uc = 0, vc = 0, wc_ = 0, mu = 0, kcd = 0, smt = 0, skt = 0;
+            if (active && visc) {
+                const Node<R> Cz = znode_at(k, 0);
+                uc = Cz.u;
+                vc = Cz.v;
+                wc_ = Cz.w;
+                const R Tc = Cz.T;
+                mu = visc_pow<R>(Tc, gas) * R(gas.ire);
+                smt = R(gas.s) * rcpr<R>(Tc);
+                if constexpr (THERMO) {   // k = mu c_p(T) / Pr, grad k = k (s/T + c_p'/c_p) grad T
+                    const double cpr = tp_cpR(gas, double(Tc));
+                    kcd = mu * R(gas.igM2 * cpr * gas.ipr);
+                    skt = smt + R(tp_dcpR(gas, double(Tc)) / cpr);
+                } else {
+                    kcd = mu * R(gas.cp * gas.ipr);
+                    skt = smt;
+                }
+                vmu[tid] = mu;
+            }
+            __syncthreads();                                   // 1: plane k+S staged
+            arrive(k + S);
+            R acc[NV] = {0, 0, 0, 0, 0};
+            R gx[4], gy[4], gz[4], dd[4];
+            auto gx_ = [&](int t) { return getx(k, t); };
+            auto gy_ = [&](int t) { return gety(k, t); };
+            auto gz_ = [&](int t) { return znode_at(k, t); };
+            if (active && visc) {
+                stencil_dir<SC, SV, 0, false, true>(gx_, dxi, dxi * dxi, R(0), acc, gx, dd);
+                visc_linear<0>(dd, mu, kcd, uc, vc, wc_, acc);
+            }
+            // the loads of plane k+S+1 go out here, after the x stencil,
+            // rather than with the convective role's just after the barrier:
+            // spreading the two roles' load bursts over the phase measured
+            // 9 % faster per launch on MI355X
+            sched_fence();
+            if (k + 1 < k1) fetch(fb, k + 1 + S);
+            sched_fence();
+            if (active && visc) {
+                stencil_dir<SC, SV, 1, false, true>(gy_, ey, ey * ey, eyy, acc, gy, dd);
+                visc_linear<1>(dd, mu, kcd, uc, vc, wc_, acc);
+            }
+            if (active && visc) {
+                stencil_dir<SC, SV, 2, false, true>(gz_, dzi, dzi * dzi, R(0), acc, gz, dd);
+                visc_linear<2>(dd, mu, kcd, uc, vc, wc_, acc);
+            }
+            if (active && visc) {
+                // mixed z parts of mu/3 d_i(div u): d_z d_x w, d_z d_y w,
+                // d_z (d_x u + d_y v) (the x-y parts are the convective role's)
+                const R m3 = mu * R(1.0 / 3.0);
+                const R mx = m3 * (dzi * d1c<SV, S>(m0));
+                const R my = m3 * (dzi * d1c<SV, S>(m1));
+                const R mz = m3 * (dzi * d1c<SV, S>(m2));
+                acc[1] += mx;
+                acc[2] += my;
+                acc[3] += mz;
+                acc[4] += uc * mx + vc * my + wc_ * mz;
+                // nonlinear parts: grad mu (= s mu/T grad T) terms and dissipation
+                const R g00 = gx[0], g10 = gx[1], g20 = gx[2], Tx = gx[3];
+                const R g01 = gy[0], g11 = gy[1], g21 = gy[2], Ty = gy[3];
+                const R g02 = gz[0], g12 = gz[1], g22 = gz[2], Tz = gz[3];
+                const R th = g00 + g11 + g22;
+                const R smu = smt * mu;
+                const R dmu0 = smu * Tx, dmu1 = smu * Ty, dmu2 = smu * Tz;
+                const R t3 = R(2.0 / 3.0);
+                const R s01 = g01 + g10, s02 = g02 + g20, s12 = g12 + g21;
+                const R N0 = dmu0 * (R(2) * g00 - t3 * th) + dmu1 * s01 + dmu2 * s02;
+                const R N1 = dmu0 * s01 + dmu1 * (R(2) * g11 - t3 * th) + dmu2 * s12;
+                const R N2 = dmu0 * s02 + dmu1 * s12 + dmu2 * (R(2) * g22 - t3 * th);
+                const R diss = mu * ((R(2) * g00 - t3 * th) * g00 + (R(2) * g11 - t3 * th) * g11 +
+                                     (R(2) * g22 - t3 * th) * g22 + s01 * s01 + s02 * s02 + s12 * s12);
+                acc[1] += N0;
+                acc[2] += N1;
+                acc[3] += N2;
+                acc[4] += uc * N0 + vc * N1 + wc_ * N2 + diss + (skt * kcd) * (Tx * Tx + Ty * Ty + Tz * Tz);
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) xch[v][tid] = acc[v];
+            __syncthreads();                                   // 2: viscous part ready
+            shift();
+        }
+    }
+    if (g.fpart) force_partial<2 * NR>(sm.fred, NR, fsum, g);
+}
+
 template <int S, int TX, int TY, typename R, bool SPLIT>
 struct SmemOf {
     using type = Smem<S, TX, TY, R>;
@@ -1297,6 +1723,12 @@ template <int S, int TX, int TY, typename R>
 struct SmemOf<S, TX, TY, R, true> {
     using type = SmemSplit<S, TX, TY, R>;
 };
+// the single-block FP64 kernels run the plane-ring march
+template <int S, int TX, int TY, typename R, bool SPLIT>
+struct RingOf {
+    static constexpr bool value = SPLIT && std::is_same<R, double>::value;
+    using type = typename std::conditional<value, SmemRing<S, TX, TY>, typename SmemOf<S, TX, TY, R, SPLIT>::type>::type;
+};
 
 template <int SC, int SV, int TX, int TY, int WPE, typename R, bool UPD, bool PIMG, bool SPLIT, int VAR = 0>
 __global__ void __attribute__((amdgpu_flat_work_group_size(TX * TY * (SPLIT ? 2 : 1), TX * TY * (SPLIT ? 2 : 1)),
@@ -1304,9 +1736,13 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(TX * TY * (SPLIT ? 2 
 k_rhs_central(const double* __restrict__ W, double* __restrict__ out, double* __restrict__ Rp,
               KGrid g, KGas gas, StepCoef sc, unsigned mask, int kc)
 {
-    __shared__ typename SmemOf<Halo<SC, SV>::S, TX, TY, R, SPLIT>::type sm;
+    using RO = RingOf<Halo<SC, SV>::S, TX, TY, R, SPLIT>;
+    __shared__ typename RO::type sm;
     const int k0 = blockIdx.z * kc;
-    if constexpr (SPLIT)
+    if constexpr (RO::value)
+        march_ring<SC, SV, TX, TY, UPD, PIMG, VAR>(sm, W, out, Rp, g, gas, sc, mask, blockIdx.x * TX,
+                                                   blockIdx.y * TY, k0, min(k0 + kc, g.nz));
+    else if constexpr (SPLIT)
         march_split<SC, SV, TX, TY, R, UPD, PIMG, VAR>(sm, W, out, Rp, g, gas, sc, mask, blockIdx.x * TX,
                                                        blockIdx.y * TY, k0, min(k0 + kc, g.nz));
     else
