@@ -1723,10 +1723,12 @@ template <int S, int TX, int TY, typename R>
 struct SmemOf<S, TX, TY, R, true> {
     using type = SmemSplit<S, TX, TY, R>;
 };
-// the single-block FP64 kernels run the plane-ring march
+// FP64 kernels run the plane-ring march wherever its working set fits the
+// 160 KB of LDS of a CU (every single-block tile; the 32-wide batch tiles)
 template <int S, int TX, int TY, typename R, bool SPLIT>
 struct RingOf {
-    static constexpr bool value = SPLIT && std::is_same<R, double>::value;
+    static constexpr bool value =
+        SPLIT && std::is_same<R, double>::value && sizeof(SmemRing<S, TX, TY>) + 64 <= 160 * 1024;
     using type = typename std::conditional<value, SmemRing<S, TX, TY>, typename SmemOf<S, TX, TY, R, SPLIT>::type>::type;
 };
 
@@ -1763,7 +1765,8 @@ k_rhs_batch(const double* __restrict__ Wsrc, double* __restrict__ Wdst, double* 
             int* __restrict__ counter, const double* __restrict__ dtp, double gk, double zk,
             int substep)
 {
-    __shared__ typename SmemOf<S, TX, TY, R, SPLIT>::type sm;
+    using RO = RingOf<S, TX, TY, R, SPLIT>;
+    __shared__ typename RO::type sm;
     __shared__ int cur;
     const double dt = *dtp;
     const StepCoef sc{dt * gk, dt * zk, substep > 0 ? 1 : 0, substep < 2 ? 1 : 0};
@@ -1775,7 +1778,10 @@ k_rhs_batch(const double* __restrict__ Wsrc, double* __restrict__ Wdst, double* 
         if (t >= ntiles) break;
         const TileDesc td = tiles[t];
         const BoxDesc& bd = boxes[td.box];
-        if constexpr (SPLIT)
+        if constexpr (RO::value)
+            march_ring<S, S, TX, TY, true, true>(sm, Wsrc + bd.woff, Wdst + bd.woff, Rp + bd.roff, bd.g, bd.gas,
+                                                 sc, (unsigned)SX_ALL, td.i0, td.j0, td.k0, td.k1);
+        else if constexpr (SPLIT)
             march_split<S, S, TX, TY, R, true, true>(sm, Wsrc + bd.woff, Wdst + bd.woff, Rp + bd.roff, bd.g,
                                                   bd.gas, sc, (unsigned)SX_ALL, td.i0, td.j0, td.k0, td.k1);
         else
