@@ -38,6 +38,11 @@ ALG_BYTES_PER_POINT_STEP = 400.0
 SUBSTEPS = 3
 
 
+def progress(msg):
+    """A progress line on stderr (the JSON result stays the only stdout line)."""
+    print(msg, file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,6 +65,8 @@ def parse():
                     help="add the viscous-order (C6 V2..V8), WENO-order (W1..W7 on every face), "
                          "thread-masking (the four grids of the paper's masking study) and "
                          "grid-size (0.25 M to 134 M points) sweeps")
+    ap.add_argument("--weno-order-only", action="store_true",
+                    help="run only the WENO-order sweep and print it (counter runs)")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON autotune cache of the batched form (default: tune afresh)")
     return ap.parse_args()
@@ -264,6 +271,7 @@ def bench_order_sweep(args, Wn, dt):
             del h
             torch.cuda.empty_cache()
         out[f"C{order}V{order}"] = row
+        progress(f"order sweep C{order}V{order} done")
     return out
 
 
@@ -284,6 +292,7 @@ def bench_visc_order_sweep(args, Wn, dt):
         out[f"C6V{vo}"] = {"ms_per_step": ms, "launch_ms": kms,
                            "roofline_frac": ALG_BYTES_PER_POINT_STEP / SUBSTEPS * case.points
                            / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, "state_ok": d.status == sx.SX_OK}
+        progress(f"viscous-order sweep C6V{vo} done")
         del h
         torch.cuda.empty_cache()
     return out
@@ -309,6 +318,7 @@ def bench_weno_order_sweep(args):
         d = h.sx_diagnostics()
         out[f"W{wo}"] = {"ms_per_step": ms, "central_kernel_ms": kms,
                          "weno_face_fraction": list(d.weno_fraction), "state_ok": d.status == sx.SX_OK}
+        progress(f"WENO-order sweep W{wo} done")
         del h, Wo
         torch.cuda.empty_cache()
     return out
@@ -340,6 +350,7 @@ def bench_thread_masking(args):
             del h, Wo
             torch.cuda.empty_cache()
         out[f"grid{n}"] = row
+        progress(f"thread-masking grid {n} done")
     return out
 
 
@@ -364,6 +375,7 @@ def bench_grid_size_sweep(args):
                                   "fused_kernel_ms": kms}
         del h, Wo
         torch.cuda.empty_cache()
+        progress(f"grid-size sweep {nx}x{ny}x{nz} done")
     return out
 
 
@@ -395,6 +407,7 @@ def bench_activation_sweep(args):
                             "weno_face_fraction": [float(f.mean()) for f in flags],
                             "state_ok": d.status == sx.SX_OK}
         del h, flags
+        progress(f"WENO-activation sweep {frac:g} done")
         torch.cuda.empty_cache()
     base = out["0"]["ms_per_step"]
     for v in out.values():
@@ -489,6 +502,9 @@ def main():
     import torch
     from paper_2304_05494_amd import inputs, sx
 
+    if args.weno_order_only:
+        print(json.dumps({"weno_order_sweep": bench_weno_order_sweep(args)}), flush=True)
+        return
     case = inputs.channel_case()
     Wn = np.ascontiguousarray(inputs.fields(case))
     h = sx.Handle(case)
