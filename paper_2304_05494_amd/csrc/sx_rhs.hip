@@ -1214,7 +1214,6 @@ __device__ __forceinline__ void march_split(SmemSplit<Halo<SC, SV>::S, TX, TY, R
 
         int slot_k = S;
         for (int k = k0; k < k1; ++k) {
-            const int slot_new = slot_k + S >= Q ? slot_k + S - Q : slot_k + S;
             stage_arrival(fa);
             // viscosity of plane k from this thread's own ring record
             R uc = 0, vc = 0, wc_ = 0, mu = 0, kcd = 0, smt = 0, skt = 0;
@@ -1830,7 +1829,9 @@ struct Tile {
     static constexpr int TX = SPLIT ? 32 : 64;
     static constexpr int TY = S <= 3 ? 8 : 4;
     static constexpr int NTH = TX * TY * (SPLIT ? 2 : 1);
-    static constexpr int WPE = 2;
+    // waves per SIMD: FP64 at S = 4 holds a whole CU's LDS with one
+    // 256-thread workgroup, so its waves may use the full register file
+    static constexpr int WPE = (!F32 && S > 3) ? 1 : 2;
 };
 
 // Bulk forcing (the paper's force_rhs_1 sum reduction): f = -sum V R_rhou /

@@ -4,10 +4,12 @@
 //
 // The fused kernel (sx_rhs.hip) applies the central split-form flux on every
 // face. This pass then corrects the flagged faces only, in three steps:
-//   1. k_flags: every node decides the flags of the faces it owns (the face
-//      after it along each direction, plus the first face of each line) and
-//      appends flagged faces to one list per direction and itself to a node
-//      list when any of its six faces is flagged (one atomic per wave);
+//   1. k_flaglist (after k_theta): every node decides the flags of its six
+//      faces, writes those it owns (the face after it along each direction,
+//      plus the first face of each line), appends its owned flagged faces to
+//      one list per direction and itself to a node list when any of its six
+//      faces is flagged (one atomic per list per workgroup); injected flags
+//      are listed by k_lists;
 //   2. k_weno_face: one thread per flagged face evaluates
 //      dF = F_weno - F_central once and stores it by face index, so the
 //      wave's lanes all run the same characteristic-flux code (no per-node
@@ -106,79 +108,9 @@ __global__ void __launch_bounds__(TXT * TYT) k_theta(KGrid g, double eps, const 
 }
 
 // Face flags: f[d] holds n_d + 1 faces per line (entry f is the face
-// between nodes f-1 and f). Node (i, j, k) decides the face after it along
-// each direction and, for i = 0 (j = 0, k = 0), the first face of its line:
-// flagged iff the largest theta over the 2r nodes of the face's stencil
-// exceeds the threshold. A workgroup owns an FX x FY column tile and
-// marches a chunk of FZ planes: theta of the plane with an r-wide x/y halo
-// sits in LDS (x and y maxima), each thread keeps its column's last 2r
-// theta values in registers (z maxima).
-constexpr int FX = 64, FY = 8, RMAX = 4, FZ = 16;   // tile and z-chunk of k_flags
-__global__ void __launch_bounds__(FX * FY) k_flags(KGrid g, int r, double thr,
-                                                   const double* __restrict__ theta, WenoBufs b)
-{
-    constexpr int HXF = FX + 2 * RMAX, HYF = FY + 2 * RMAX;
-    __shared__ double pl[HYF][HXF];
-    const int tx = threadIdx.x % FX, ty = threadIdx.x / FX;
-    const int i0 = blockIdx.x * FX, j0 = blockIdx.y * FY;
-    const int i = i0 + tx, j = j0 + ty;
-    const bool active = i < g.nx && j < g.ny;
-    auto th = [&](int a, int bb, int c) -> double {
-        const int ia = map_ghost(a, g.nx, g.bc[0], g.bc[1]);
-        const int jb = map_ghost(bb, g.ny, g.bc[2], g.bc[3]);
-        const int kc = map_ghost(c, g.nz, g.bc[4], g.bc[5]);
-        return theta[((long long)kc * g.ny + jb) * g.nx + ia];
-    };
-    const int ic = active ? i : 0, jc = active ? j : 0;
-    const int k0 = blockIdx.z * FZ, k1 = min(k0 + FZ, g.nz);
-    double win[2 * RMAX];   // theta of this column at planes k-r+1 .. k+r
-#pragma unroll
-    for (int t = 0; t < 2 * RMAX; ++t) win[t] = 0.0;
-    for (int t = 0; t < 2 * r; ++t) win[t] = th(ic, jc, k0 - r + t);   // planes k0-r .. k0+r-1
-    const long long sfz = (long long)g.ny * g.nx;
-    if (active && k0 == 0) {
-        double mx = 0.0;
-        for (int t = 0; t < 2 * r; ++t) mx = win[t] > mx ? win[t] : mx;
-        b.f[2][(long long)j * g.nx + i] = mx > thr ? 1 : 0;        // face -1/2 of the z line
-    }
-    for (int k = k0; k < k1; ++k) {
-        // shift the window to planes k-r+1 .. k+r
-        for (int t = 0; t < 2 * r - 1; ++t) win[t] = win[t + 1];
-        win[2 * r - 1] = th(ic, jc, k + r);
-        __syncthreads();
-        for (int q = threadIdx.x; q < HXF * HYF; q += FX * FY) {
-            const int hx = q % HXF, hy = q / HXF;
-            const int a = i0 - RMAX + hx, bb = j0 - RMAX + hy;
-            // only the r-wide halo is read (and mapped: r <= ghost width <= n)
-            pl[hy][hx] = (a >= -r && a < g.nx + r && bb >= -r && bb < g.ny + r) ? th(a, bb, k) : 0.0;
-        }
-        __syncthreads();
-        if (!active) continue;
-        const int cx = tx + RMAX, cy = ty + RMAX;
-        double mx = 0.0, my = 0.0, mz = 0.0;
-        for (int t = -r + 1; t <= r; ++t) {
-            mx = fmax(mx, pl[cy][cx + t]);
-            my = fmax(my, pl[cy + t][cx]);
-        }
-        for (int t = 0; t < 2 * r; ++t) mz = fmax(mz, win[t]);
-        const long long ix = ((long long)k * g.ny + j) * (g.nx + 1) + i;
-        const long long iy = ((long long)k * (g.ny + 1) + j) * g.nx + i;
-        const long long iz = ((long long)k * g.ny + j) * g.nx + i;
-        b.f[0][ix + 1] = mx > thr ? 1 : 0;
-        b.f[1][iy + g.nx] = my > thr ? 1 : 0;
-        b.f[2][iz + sfz] = mz > thr ? 1 : 0;
-        if (i == 0) {   // face -1/2 of the x line: nodes -r .. r-1
-            double m0 = 0.0;
-            for (int t = -r; t <= r - 1; ++t) m0 = fmax(m0, pl[cy][cx + t]);
-            b.f[0][ix] = m0 > thr ? 1 : 0;
-        }
-        if (j == 0) {
-            double m0 = 0.0;
-            for (int t = -r; t <= r - 1; ++t) m0 = fmax(m0, pl[cy + t][cx]);
-            b.f[1][iy] = m0 > thr ? 1 : 0;
-        }
-    }
-}
+// between nodes f-1 and f); a face is flagged iff the largest theta over
+// the 2r nodes of its WENO stencil exceeds the threshold.
+constexpr int RMAX = 4;   // largest WENO half-width (W7)
 
 // Wave-aggregated append into a workgroup's LDS cursor: returns this lane's
 // slot (relative to the workgroup's block of the list) or -1.
@@ -248,6 +180,120 @@ __global__ void __launch_bounds__(WB) k_lists(KGrid g, WenoBufs b)
     }
     __syncthreads();
     visit(true);
+}
+
+// Flags and lists in one pass (the sensor path; injected flags go through
+// k_lists). A workgroup owns a GX x GY column tile and marches a chunk of
+// GZ planes: theta of the plane with an r-wide x/y halo sits in LDS (x and
+// y maxima), each thread keeps its column's last 2r+1 theta values in
+// registers (z maxima). Every node decides all six of its faces
+// (the "+" faces it owns and the "-" faces, whose windows it reads from the
+// same LDS plane and register window), so it knows at once which faces it
+// lists and whether it is a listed node. Those bits stay in LDS over the
+// chunk while the workgroup counts its entries; one global atomic per list
+// then reserves its share and a second sweep over the bits writes the
+// entries. A face's flag is written by the node after it (and the first
+// face of each line by the line's first node).
+constexpr int GX = 64, GY = 8, GZ = 32;
+__global__ void __launch_bounds__(GX * GY) k_flaglist(KGrid g, int r, double thr,
+                                                      const double* __restrict__ theta, WenoBufs b)
+{
+    constexpr int HXF = GX + 2 * RMAX, HYF = GY + 2 * RMAX;
+    __shared__ double pl[HYF][HXF];
+    __shared__ unsigned char bits[GZ][GX * GY];   // owned flagged faces x+, x-, y+, y-, z+, z-; bit 6: listed node
+    __shared__ int cur[4], base[4];
+    if (threadIdx.x < 4) cur[threadIdx.x] = 0;
+    const int tx = threadIdx.x % GX, ty = threadIdx.x / GX;
+    const int i0 = blockIdx.x * GX, j0 = blockIdx.y * GY;
+    const int i = i0 + tx, j = j0 + ty;
+    const bool active = i < g.nx && j < g.ny;
+    auto th = [&](int a, int bb, int c) -> double {
+        const int ia = map_ghost(a, g.nx, g.bc[0], g.bc[1]);
+        const int jb = map_ghost(bb, g.ny, g.bc[2], g.bc[3]);
+        const int kc = map_ghost(c, g.nz, g.bc[4], g.bc[5]);
+        return theta[((long long)kc * g.ny + jb) * g.nx + ia];
+    };
+    const int ic = active ? i : 0, jc = active ? j : 0;
+    const int k0 = blockIdx.z * GZ, k1 = min(k0 + GZ, g.nz);
+    double win[2 * RMAX + 1];   // theta of this column at planes k-r .. k+r
+#pragma unroll
+    for (int t = 0; t <= 2 * RMAX; ++t) win[t] = 0.0;
+    for (int t = 1; t <= 2 * r; ++t) win[t] = th(ic, jc, k0 - r - 1 + t);   // planes k0-r .. k0+r-1
+    const long long sfz = (long long)g.ny * g.nx;
+    auto wave_count = [&](bool pred, int* c) {
+        const unsigned long long m = __ballot(pred);
+        if (m && __lane_id() == __ffsll((long long)m) - 1) atomicAdd(c, __popcll(m));
+    };
+    for (int k = k0; k < k1; ++k) {
+        for (int t = 0; t < 2 * r; ++t) win[t] = win[t + 1];
+        win[2 * r] = th(ic, jc, k + r);
+        __syncthreads();
+        for (int q = threadIdx.x; q < HXF * HYF; q += GX * GY) {
+            const int hx = q % HXF, hy = q / HXF;
+            const int a = i0 - RMAX + hx, bb = j0 - RMAX + hy;
+            pl[hy][hx] = (a >= -r && a < g.nx + r && bb >= -r && bb < g.ny + r) ? th(a, bb, k) : 0.0;
+        }
+        __syncthreads();
+        unsigned char bt = 0;
+        if (active) {
+            const int cx = tx + RMAX, cy = ty + RMAX;
+            // "+" face: nodes -r+1 .. r around the node; "-" face: -r .. r-1
+            double xp = 0.0, yp = 0.0, xm = pl[cy][cx - r], ym = pl[cy - r][cx];
+            for (int t = -r + 1; t <= r - 1; ++t) {
+                xp = fmax(xp, pl[cy][cx + t]);
+                yp = fmax(yp, pl[cy + t][cx]);
+            }
+            xm = fmax(xm, xp);
+            ym = fmax(ym, yp);
+            xp = fmax(xp, pl[cy][cx + r]);
+            yp = fmax(yp, pl[cy + r][cx]);
+            double zp = 0.0, zm = win[0];
+            for (int t = 1; t < 2 * r; ++t) zp = fmax(zp, win[t]);
+            zm = fmax(zm, zp);
+            zp = fmax(zp, win[2 * r]);
+            const bool fxp = xp > thr, fxm = xm > thr, fyp = yp > thr, fym = ym > thr;
+            const bool fzp = zp > thr, fzm = zm > thr;
+            const long long ix = ((long long)k * g.ny + j) * (g.nx + 1) + i;
+            const long long iy = ((long long)k * (g.ny + 1) + j) * g.nx + i;
+            const long long iz = ((long long)k * g.ny + j) * g.nx + i;
+            b.f[0][ix + 1] = fxp;
+            b.f[1][iy + g.nx] = fyp;
+            b.f[2][iz + sfz] = fzp;
+            if (i == 0) b.f[0][ix] = fxm;
+            if (j == 0) b.f[1][iy] = fym;
+            if (k == 0) b.f[2][iz] = fzm;
+            bt = (unsigned char)(fxp | ((i == 0 && fxm) << 1) | (fyp << 2) | ((j == 0 && fym) << 3) | (fzp << 4) |
+                                 ((k == 0 && fzm) << 5) | ((fxp || fxm || fyp || fym || fzp || fzm) << 6));
+        }
+        bits[k - k0][threadIdx.x] = bt;
+        wave_count(bt & 1, &cur[0]);
+        wave_count(bt & 2, &cur[0]);
+        wave_count(bt & 4, &cur[1]);
+        wave_count(bt & 8, &cur[1]);
+        wave_count(bt & 16, &cur[2]);
+        wave_count(bt & 32, &cur[2]);
+        wave_count(bt & 64, &cur[3]);
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        base[threadIdx.x] = cur[threadIdx.x] ? atomicAdd(&b.counts[threadIdx.x], cur[threadIdx.x]) : 0;
+        cur[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    for (int k = k0; k < k1; ++k) {
+        const unsigned bt = bits[k - k0][threadIdx.x];
+        const long long ix = ((long long)k * g.ny + j) * (g.nx + 1) + i;
+        const long long iy = ((long long)k * (g.ny + 1) + j) * g.nx + i;
+        const long long iz = ((long long)k * g.ny + j) * g.nx + i;
+        const long long e[6] = {ix + 1, ix, iy + g.nx, iy, iz + sfz, iz};
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const int slot = wave_slot((bt >> q) & 1, &cur[q / 2]);
+            if (slot >= 0) b.flist[q / 2][base[q / 2] + slot] = (int)e[q];
+        }
+        const int slot = wave_slot((bt >> 6) & 1, &cur[3]);
+        if (slot >= 0) b.nlist[base[3] + slot] = (int)iz;
+    }
 }
 
 __global__ void k_zero_counts(int* p)
@@ -629,9 +675,10 @@ hipError_t launch_sensor_flags(const KGrid& g, const KScheme& sc, const double* 
         const dim3 tgrid((unsigned)((g.nx + TXT - 1) / TXT), (unsigned)((g.ny + TYT - 1) / TYT),
                          (unsigned)((g.nz + TZT - 1) / TZT));
         hipLaunchKernelGGL(k_theta, tgrid, dim3(TXT * TYT), 0, st, g, sc.sensor_eps, W, b.theta);
-        const dim3 fgrid((unsigned)((g.nx + FX - 1) / FX), (unsigned)((g.ny + FY - 1) / FY),
-                         (unsigned)((g.nz + FZ - 1) / FZ));
-        hipLaunchKernelGGL(k_flags, fgrid, dim3(FX * FY), 0, st, g, sc.r, sc.sensor_thr, b.theta, b);
+        const dim3 fgrid((unsigned)((g.nx + GX - 1) / GX), (unsigned)((g.ny + GY - 1) / GY),
+                         (unsigned)((g.nz + GZ - 1) / GZ));
+        hipLaunchKernelGGL(k_flaglist, fgrid, dim3(GX * GY), 0, st, g, sc.r, sc.sensor_thr, b.theta, b);
+        return hipGetLastError();
     }
     const long long per = (long long)WB * LPT;
     hipLaunchKernelGGL(k_lists, dim3((unsigned)((g.nint + per - 1) / per)), dim3(WB), 0, st, g, b);
