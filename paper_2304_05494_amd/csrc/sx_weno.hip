@@ -110,7 +110,6 @@ __global__ void __launch_bounds__(TXT * TYT) k_theta(KGrid g, double eps, const 
 // Face flags: f[d] holds n_d + 1 faces per line (entry f is the face
 // between nodes f-1 and f); a face is flagged iff the largest theta over
 // the 2r nodes of its WENO stencil exceeds the threshold.
-constexpr int RMAX = 4;   // largest WENO half-width (W7)
 
 // Wave-aggregated append into a workgroup's LDS cursor: returns this lane's
 // slot (relative to the workgroup's block of the list) or -1.
@@ -195,10 +194,12 @@ __global__ void __launch_bounds__(WB) k_lists(KGrid g, WenoBufs b)
 // entries. A face's flag is written by the node after it (and the first
 // face of each line by the line's first node).
 constexpr int GX = 64, GY = 8, GZ = 32;
-__global__ void __launch_bounds__(GX * GY) k_flaglist(KGrid g, int r, double thr,
-                                                      const double* __restrict__ theta, WenoBufs b)
+template <int RW>
+__global__ void __launch_bounds__(GX * GY) k_flaglist(KGrid g, double thr, const double* __restrict__ theta,
+                                                      WenoBufs b)
 {
-    constexpr int HXF = GX + 2 * RMAX, HYF = GY + 2 * RMAX;
+    constexpr int HXF = GX + 2 * RW, HYF = GY + 2 * RW, HPF = HXF * HYF;
+    constexpr int NPF = (HPF + GX * GY - 1) / (GX * GY);
     __shared__ double pl[HYF][HXF];
     __shared__ unsigned char bits[GZ][GX * GY];   // owned flagged faces x+, x-, y+, y-, z+, z-; bit 6: listed node
     __shared__ int cur[4], base[4];
@@ -207,65 +208,85 @@ __global__ void __launch_bounds__(GX * GY) k_flaglist(KGrid g, int r, double thr
     const int i0 = blockIdx.x * GX, j0 = blockIdx.y * GY;
     const int i = i0 + tx, j = j0 + ty;
     const bool active = i < g.nx && j < g.ny;
-    auto th = [&](int a, int bb, int c) -> double {
-        const int ia = map_ghost(a, g.nx, g.bc[0], g.bc[1]);
-        const int jb = map_ghost(bb, g.ny, g.bc[2], g.bc[3]);
-        const int kc = map_ghost(c, g.nz, g.bc[4], g.bc[5]);
-        return theta[((long long)kc * g.ny + jb) * g.nx + ia];
-    };
-    const int ic = active ? i : 0, jc = active ? j : 0;
     const int k0 = blockIdx.z * GZ, k1 = min(k0 + GZ, g.nz);
-    double win[2 * RMAX + 1];   // theta of this column at planes k-r .. k+r
+    const long long psz = (long long)g.ny * g.nx;
+    // in-plane offsets of this thread's halo points (x and y mapped once;
+    // ghost positions take theta of their periodic image or mirror node)
+    // and of its own column; the plane part is uniform
+    int hoff[NPF];
 #pragma unroll
-    for (int t = 0; t <= 2 * RMAX; ++t) win[t] = 0.0;
-    for (int t = 1; t <= 2 * r; ++t) win[t] = th(ic, jc, k0 - r - 1 + t);   // planes k0-r .. k0+r-1
-    const long long sfz = (long long)g.ny * g.nx;
+    for (int a = 0; a < NPF; ++a) {
+        const int q = threadIdx.x + a * GX * GY;
+        const int x = min(i0 - RW + q % HXF, g.nx + RW - 1), y = min(j0 - RW + q / HXF, g.ny + RW - 1);
+        hoff[a] = map_ghost(y, g.ny, g.bc[2], g.bc[3]) * g.nx + map_ghost(x, g.nx, g.bc[0], g.bc[1]);
+    }
+    const int coff = (active ? j : 0) * g.nx + (active ? i : 0);
+    auto plane = [&](int k) { return theta + map_ghost(k, g.nz, g.bc[4], g.bc[5]) * psz; };
+    double win[2 * RW + 1];   // theta of this column at planes k-r .. k+r
+#pragma unroll
+    for (int t = 1; t <= 2 * RW; ++t) win[t] = plane(k0 - RW - 1 + t)[coff];   // planes k0-r .. k0+r-1
+    win[0] = 0.0;
     auto wave_count = [&](bool pred, int* c) {
         const unsigned long long m = __ballot(pred);
         if (m && __lane_id() == __ffsll((long long)m) - 1) atomicAdd(c, __popcll(m));
     };
+    // theta of the next plane (this thread's halo points, its column's new
+    // window value) is loaded while the current plane is decided
+    double hv[NPF], wv;
+    auto load_plane = [&](int k) {
+        const double* tp = plane(k);
+#pragma unroll
+        for (int a = 0; a < NPF; ++a)
+            if (a + 1 < NPF || threadIdx.x + a * GX * GY < HPF) hv[a] = tp[hoff[a]];
+        wv = plane(k + RW)[coff];
+    };
+    // per-thread parts of the face indices (k-independent)
+    const int fxo = j * (g.nx + 1) + i, fyo = j * g.nx + i;
+    const long long fxk = (long long)g.ny * (g.nx + 1), fyk = (long long)(g.ny + 1) * g.nx;
+    load_plane(k0);
     for (int k = k0; k < k1; ++k) {
-        for (int t = 0; t < 2 * r; ++t) win[t] = win[t + 1];
-        win[2 * r] = th(ic, jc, k + r);
+#pragma unroll
+        for (int t = 0; t < 2 * RW; ++t) win[t] = win[t + 1];
+        win[2 * RW] = wv;
         __syncthreads();
-        for (int q = threadIdx.x; q < HXF * HYF; q += GX * GY) {
-            const int hx = q % HXF, hy = q / HXF;
-            const int a = i0 - RMAX + hx, bb = j0 - RMAX + hy;
-            pl[hy][hx] = (a >= -r && a < g.nx + r && bb >= -r && bb < g.ny + r) ? th(a, bb, k) : 0.0;
+#pragma unroll
+        for (int a = 0; a < NPF; ++a) {
+            const int q = threadIdx.x + a * GX * GY;
+            if (a + 1 < NPF || q < HPF) pl[q / HXF][q % HXF] = hv[a];
         }
         __syncthreads();
-        unsigned char bt = 0;
+        if (k + 1 < k1) load_plane(k + 1);
+        unsigned bt = 0;
         if (active) {
-            const int cx = tx + RMAX, cy = ty + RMAX;
+            const int cx = tx + RW, cy = ty + RW;
             // "+" face: nodes -r+1 .. r around the node; "-" face: -r .. r-1
-            double xp = 0.0, yp = 0.0, xm = pl[cy][cx - r], ym = pl[cy - r][cx];
-            for (int t = -r + 1; t <= r - 1; ++t) {
+            double xp = 0.0, yp = 0.0, zp = 0.0;
+#pragma unroll
+            for (int t = -RW + 1; t <= RW - 1; ++t) {
                 xp = fmax(xp, pl[cy][cx + t]);
                 yp = fmax(yp, pl[cy + t][cx]);
             }
-            xm = fmax(xm, xp);
-            ym = fmax(ym, yp);
-            xp = fmax(xp, pl[cy][cx + r]);
-            yp = fmax(yp, pl[cy + r][cx]);
-            double zp = 0.0, zm = win[0];
-            for (int t = 1; t < 2 * r; ++t) zp = fmax(zp, win[t]);
-            zm = fmax(zm, zp);
-            zp = fmax(zp, win[2 * r]);
+#pragma unroll
+            for (int t = 1; t < 2 * RW; ++t) zp = fmax(zp, win[t]);
+            const double xm = fmax(pl[cy][cx - RW], xp), ym = fmax(pl[cy - RW][cx], yp), zm = fmax(win[0], zp);
+            xp = fmax(xp, pl[cy][cx + RW]);
+            yp = fmax(yp, pl[cy + RW][cx]);
+            zp = fmax(zp, win[2 * RW]);
             const bool fxp = xp > thr, fxm = xm > thr, fyp = yp > thr, fym = ym > thr;
             const bool fzp = zp > thr, fzm = zm > thr;
-            const long long ix = ((long long)k * g.ny + j) * (g.nx + 1) + i;
-            const long long iy = ((long long)k * (g.ny + 1) + j) * g.nx + i;
-            const long long iz = ((long long)k * g.ny + j) * g.nx + i;
-            b.f[0][ix + 1] = fxp;
-            b.f[1][iy + g.nx] = fyp;
-            b.f[2][iz + sfz] = fzp;
-            if (i == 0) b.f[0][ix] = fxm;
-            if (j == 0) b.f[1][iy] = fym;
-            if (k == 0) b.f[2][iz] = fzm;
-            bt = (unsigned char)(fxp | ((i == 0 && fxm) << 1) | (fyp << 2) | ((j == 0 && fym) << 3) | (fzp << 4) |
-                                 ((k == 0 && fzm) << 5) | ((fxp || fxm || fyp || fym || fzp || fzm) << 6));
+            unsigned char* const fx = b.f[0] + k * fxk;
+            unsigned char* const fy = b.f[1] + k * fyk;
+            unsigned char* const fz = b.f[2] + k * psz;
+            fx[fxo + 1] = fxp;
+            fy[fyo + g.nx] = fyp;
+            fz[fyo + psz] = fzp;
+            if (i == 0) fx[fxo] = fxm;
+            if (j == 0) fy[fyo] = fym;
+            if (k == 0) fz[fyo] = fzm;
+            bt = fxp | ((i == 0 && fxm) << 1) | (fyp << 2) | ((j == 0 && fym) << 3) | (fzp << 4) |
+                 ((k == 0 && fzm) << 5) | ((fxp || fxm || fyp || fym || fzp || fzm) << 6);
         }
-        bits[k - k0][threadIdx.x] = bt;
+        bits[k - k0][threadIdx.x] = (unsigned char)bt;
         wave_count(bt & 1, &cur[0]);
         wave_count(bt & 2, &cur[0]);
         wave_count(bt & 4, &cur[1]);
@@ -282,18 +303,25 @@ __global__ void __launch_bounds__(GX * GY) k_flaglist(KGrid g, int r, double thr
     __syncthreads();
     for (int k = k0; k < k1; ++k) {
         const unsigned bt = bits[k - k0][threadIdx.x];
-        const long long ix = ((long long)k * g.ny + j) * (g.nx + 1) + i;
-        const long long iy = ((long long)k * (g.ny + 1) + j) * g.nx + i;
-        const long long iz = ((long long)k * g.ny + j) * g.nx + i;
-        const long long e[6] = {ix + 1, ix, iy + g.nx, iy, iz + sfz, iz};
+        if (!__ballot(bt != 0)) continue;
+        // face and node indices fit in int (init keeps the interior below 2^29 points)
+        const int ix = (int)(k * fxk) + fxo, iy = (int)(k * fyk) + fyo, iz = (int)(k * psz) + fyo;
+        const int e[6] = {ix + 1, ix, iy + g.nx, iy, iz + (int)psz, iz};
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
             const int slot = wave_slot((bt >> q) & 1, &cur[q / 2]);
-            if (slot >= 0) b.flist[q / 2][base[q / 2] + slot] = (int)e[q];
+            if (slot >= 0) b.flist[q / 2][base[q / 2] + slot] = e[q];
         }
         const int slot = wave_slot((bt >> 6) & 1, &cur[3]);
-        if (slot >= 0) b.nlist[base[3] + slot] = (int)iz;
+        if (slot >= 0) b.nlist[base[3] + slot] = iz;
     }
+}
+
+template <int RW>
+static void launch_flaglist(const KGrid& g, double thr, const WenoBufs& b, hipStream_t st)
+{
+    const dim3 grid((unsigned)((g.nx + GX - 1) / GX), (unsigned)((g.ny + GY - 1) / GY), (unsigned)((g.nz + GZ - 1) / GZ));
+    hipLaunchKernelGGL(k_flaglist<RW>, grid, dim3(GX * GY), 0, st, g, thr, b.theta, b);
 }
 
 __global__ void k_zero_counts(int* p)
@@ -675,9 +703,12 @@ hipError_t launch_sensor_flags(const KGrid& g, const KScheme& sc, const double* 
         const dim3 tgrid((unsigned)((g.nx + TXT - 1) / TXT), (unsigned)((g.ny + TYT - 1) / TYT),
                          (unsigned)((g.nz + TZT - 1) / TZT));
         hipLaunchKernelGGL(k_theta, tgrid, dim3(TXT * TYT), 0, st, g, sc.sensor_eps, W, b.theta);
-        const dim3 fgrid((unsigned)((g.nx + GX - 1) / GX), (unsigned)((g.ny + GY - 1) / GY),
-                         (unsigned)((g.nz + GZ - 1) / GZ));
-        hipLaunchKernelGGL(k_flaglist, fgrid, dim3(GX * GY), 0, st, g, sc.r, sc.sensor_thr, b.theta, b);
+        switch (sc.r) {
+        case 1: launch_flaglist<1>(g, sc.sensor_thr, b, st); break;
+        case 2: launch_flaglist<2>(g, sc.sensor_thr, b, st); break;
+        case 3: launch_flaglist<3>(g, sc.sensor_thr, b, st); break;
+        default: launch_flaglist<4>(g, sc.sensor_thr, b, st); break;
+        }
         return hipGetLastError();
     }
     const long long per = (long long)WB * LPT;
