@@ -278,6 +278,7 @@ int sx_init(const sx_grid* grid, const sx_gas* gas, const sx_scheme* scheme, sx_
             if (e == hipSuccess) e = hipMalloc(&b.dF[d], sizeof(double) * sx::NV * nf[d]);
         }
         if (e == hipSuccess) e = hipMalloc(&b.nlist, sizeof(int) * ni);
+        if (e == hipSuccess) e = hipMalloc(&b.nmask, (size_t)ni);
         if (e == hipSuccess) e = hipMalloc(&b.counts, sizeof(int) * 4);
         if (e == hipSuccess) e = hipMalloc(&h->d_fcount, sizeof(unsigned long long) * 3);
     }
@@ -296,7 +297,7 @@ void sx_finalize(sx_handle* h)
     for (void* p : {(void*)h->d_metrics, (void*)h->d_scratch, (void*)h->d_force, (void*)b.theta, (void*)b.f[0],
                     (void*)b.f[1], (void*)b.f[2], (void*)b.flist[0], (void*)b.flist[1],
                     (void*)b.flist[2], (void*)b.dF[0], (void*)b.dF[1], (void*)b.dF[2],
-                    (void*)b.nlist, (void*)b.counts, (void*)h->d_fcount})
+                    (void*)b.nlist, (void*)b.nmask, (void*)b.counts, (void*)h->d_fcount})
         if (p) (void)hipFree(p);
     for (auto* v : {&h->ev_used, &h->ev_free})
         for (auto& p : *v) {

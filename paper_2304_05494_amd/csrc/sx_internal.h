@@ -174,6 +174,8 @@ struct WenoBufs {
     unsigned char* f[3];        // face flags per direction (n_d + 1 faces per line)
     int* flist[3];              // flagged faces per direction (face indices)
     int* nlist;                 // nodes with a flagged face (interior indices)
+    unsigned char* nmask;       // flags of each listed node's faces, in node-list order:
+                                // bits x-, x+, y-, y+, z-, z+
     int* counts;                // list lengths: faces x, y, z, nodes
     double* dF[3];              // WENO minus central flux per face, [5][faces_d]
 };

@@ -15,7 +15,7 @@
 //      wave's lanes all run the same characteristic-flux code (no per-node
 //      branching over faces and directions);
 //   3. k_weno_node: one thread per listed node gathers the dF of its flagged
-//      faces in a fixed order, dR = -scale (dF_{i+1/2} - dF_{i-1/2}) per
+//      faces (known from the node list's face masks) in a fixed order, dR = -scale (dF_{i+1/2} - dF_{i-1/2}) per
 //      direction, and adds dR to the RHS (rhs mode) or, after the fused RK
 //      update, to the new state (W' += dt gamma_k dR) and to the RK register
 //      (Rprev += dR).
@@ -142,6 +142,7 @@ __global__ void __launch_bounds__(WB) k_lists(KGrid g, WenoBufs b)
             const long long m = m0 + (long long)it * WB + threadIdx.x;
             const bool in = m < g.nint;
             bool own[6] = {false, false, false, false, false, false}, node = false;
+            unsigned nb = 0;
             long long e[6] = {0, 0, 0, 0, 0, 0};
             if (in) {
                 const int i = (int)(m % g.nx);
@@ -161,6 +162,7 @@ __global__ void __launch_bounds__(WB) k_lists(KGrid g, WenoBufs b)
                 own[4] = zp; e[4] = iz + sfz;
                 own[5] = k == 0 && zm; e[5] = iz;
                 node = xm || xp || ym || yp || zm || zp;
+                nb = xm | (xp << 1) | (ym << 2) | (yp << 3) | (zm << 4) | (zp << 5);
             }
 #pragma unroll
             for (int q = 0; q < 6; ++q) {
@@ -168,7 +170,10 @@ __global__ void __launch_bounds__(WB) k_lists(KGrid g, WenoBufs b)
                 if (write && slot >= 0) b.flist[q / 2][base[q / 2] + slot] = (int)e[q];
             }
             const int slot = wave_slot(node, &cur[3]);
-            if (write && slot >= 0) b.nlist[base[3] + slot] = (int)m;
+            if (write && slot >= 0) {
+                b.nlist[base[3] + slot] = (int)m;
+                b.nmask[base[3] + slot] = (unsigned char)nb;
+            }
         }
     };
     visit(false);
@@ -201,7 +206,7 @@ __global__ void __launch_bounds__(GX * GY) k_flaglist(KGrid g, double thr, const
     constexpr int HXF = GX + 2 * RW, HYF = GY + 2 * RW, HPF = HXF * HYF;
     constexpr int NPF = (HPF + GX * GY - 1) / (GX * GY);
     __shared__ double pl[HYF][HXF];
-    __shared__ unsigned char bits[GZ][GX * GY];   // owned flagged faces x+, x-, y+, y-, z+, z-; bit 6: listed node
+    __shared__ unsigned char bits[GZ][GX * GY];   // flags of the node's faces x-, x+, y-, y+, z-, z+
     __shared__ int cur[4], base[4];
     if (threadIdx.x < 4) cur[threadIdx.x] = 0;
     const int tx = threadIdx.x % GX, ty = threadIdx.x / GX;
@@ -243,6 +248,11 @@ __global__ void __launch_bounds__(GX * GY) k_flaglist(KGrid g, double thr, const
     // per-thread parts of the face indices (k-independent)
     const int fxo = j * (g.nx + 1) + i, fyo = j * g.nx + i;
     const long long fxk = (long long)g.ny * (g.nx + 1), fyk = (long long)(g.ny + 1) * g.nx;
+    // faces a node lists: those after it, and the first face of each line
+    auto owned = [&](unsigned bt, int k) {
+        return (bt & 0x2a) | ((bt & 1) && i == 0 ? 1u : 0u) | ((bt & 4) && j == 0 ? 4u : 0u) |
+               ((bt & 16) && k == 0 ? 16u : 0u);
+    };
     load_plane(k0);
     for (int k = k0; k < k1; ++k) {
 #pragma unroll
@@ -283,17 +293,17 @@ __global__ void __launch_bounds__(GX * GY) k_flaglist(KGrid g, double thr, const
             if (i == 0) fx[fxo] = fxm;
             if (j == 0) fy[fyo] = fym;
             if (k == 0) fz[fyo] = fzm;
-            bt = fxp | ((i == 0 && fxm) << 1) | (fyp << 2) | ((j == 0 && fym) << 3) | (fzp << 4) |
-                 ((k == 0 && fzm) << 5) | ((fxp || fxm || fyp || fym || fzp || fzm) << 6);
+            bt = fxm | (fxp << 1) | (fym << 2) | (fyp << 3) | (fzm << 4) | (fzp << 5);
         }
         bits[k - k0][threadIdx.x] = (unsigned char)bt;
-        wave_count(bt & 1, &cur[0]);
-        wave_count(bt & 2, &cur[0]);
-        wave_count(bt & 4, &cur[1]);
-        wave_count(bt & 8, &cur[1]);
-        wave_count(bt & 16, &cur[2]);
-        wave_count(bt & 32, &cur[2]);
-        wave_count(bt & 64, &cur[3]);
+        const unsigned ow = owned(bt, k);
+        wave_count(ow & 1, &cur[0]);
+        wave_count(ow & 2, &cur[0]);
+        wave_count(ow & 4, &cur[1]);
+        wave_count(ow & 8, &cur[1]);
+        wave_count(ow & 16, &cur[2]);
+        wave_count(ow & 32, &cur[2]);
+        wave_count(bt != 0, &cur[3]);
     }
     __syncthreads();
     if (threadIdx.x < 4) {
@@ -306,14 +316,18 @@ __global__ void __launch_bounds__(GX * GY) k_flaglist(KGrid g, double thr, const
         if (!__ballot(bt != 0)) continue;
         // face and node indices fit in int (init keeps the interior below 2^29 points)
         const int ix = (int)(k * fxk) + fxo, iy = (int)(k * fyk) + fyo, iz = (int)(k * psz) + fyo;
-        const int e[6] = {ix + 1, ix, iy + g.nx, iy, iz + (int)psz, iz};
+        const int e[6] = {ix, ix + 1, iy, iy + g.nx, iz, iz + (int)psz};
+        const unsigned ow = owned(bt, k);
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-            const int slot = wave_slot((bt >> q) & 1, &cur[q / 2]);
+            const int slot = wave_slot((ow >> q) & 1, &cur[q / 2]);
             if (slot >= 0) b.flist[q / 2][base[q / 2] + slot] = e[q];
         }
-        const int slot = wave_slot((bt >> 6) & 1, &cur[3]);
-        if (slot >= 0) b.nlist[base[3] + slot] = iz;
+        const int slot = wave_slot(bt != 0, &cur[3]);
+        if (slot >= 0) {
+            b.nlist[base[3] + slot] = iz;
+            b.nmask[base[3] + slot] = (unsigned char)bt;
+        }
     }
 }
 
@@ -582,6 +596,7 @@ __global__ void __launch_bounds__(WB) k_weno_node(KGrid g, unsigned mask, WenoBu
     const long long nfz = (long long)(g.nz + 1) * g.ny * g.nx;
     for (int t = blockIdx.x * WB + threadIdx.x; t < nn; t += gridDim.x * WB) {
         const long long m = b.nlist[t];
+        const unsigned nb = b.nmask[t];
         const int i = (int)(m % g.nx);
         const long long jk = m / g.nx;
         const int j = (int)(jk % g.ny);
@@ -597,8 +612,8 @@ __global__ void __launch_bounds__(WB) k_weno_node(KGrid g, unsigned mask, WenoBu
             const double scale = d == 0 ? g.dxi : (d == 1 ? g.eta_y[j] : g.dzi);
 #pragma unroll
             for (int side = 0; side < 2; ++side) {
+                if (!((nb >> (2 * d + side)) & 1)) continue;
                 const long long e = fidx[d][0] + side * step[d];
-                if (!b.f[d][e]) continue;
                 const double sg = side == 1 ? -scale : scale;
 #pragma unroll
                 for (int v = 0; v < NV; ++v) dR[v] += sg * b.dF[d][v * nface[d] + e];
