@@ -270,7 +270,7 @@ int sx_init(const sx_grid* grid, const sx_gas* gas, const sx_scheme* scheme, sx_
         const long long nf[3] = {(long long)g.nz * g.ny * (g.nx + 1), (long long)g.nz * (g.ny + 1) * g.nx,
                                  (long long)(g.nz + 1) * g.ny * g.nx};
         sx::WenoBufs& b = h->wb;
-        e = hipMalloc(&b.theta, sizeof(double) * ni);
+        e = hipMalloc(&b.sens, (size_t)ni);
         for (int d = 0; d < 3 && e == hipSuccess; ++d) {
             e = hipMalloc(&b.f[d], (size_t)nf[d]);
             if (e == hipSuccess) e = hipMemset(b.f[d], 0, (size_t)nf[d]);
@@ -294,7 +294,7 @@ void sx_finalize(sx_handle* h)
 {
     if (!h) return;
     const sx::WenoBufs& b = h->wb;
-    for (void* p : {(void*)h->d_metrics, (void*)h->d_scratch, (void*)h->d_force, (void*)b.theta, (void*)b.f[0],
+    for (void* p : {(void*)h->d_metrics, (void*)h->d_scratch, (void*)h->d_force, (void*)b.sens, (void*)b.f[0],
                     (void*)b.f[1], (void*)b.f[2], (void*)b.flist[0], (void*)b.flist[1],
                     (void*)b.flist[2], (void*)b.dF[0], (void*)b.dF[1], (void*)b.dF[2],
                     (void*)b.nlist, (void*)b.nmask, (void*)b.counts, (void*)h->d_fcount})

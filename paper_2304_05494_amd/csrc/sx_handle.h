@@ -30,7 +30,7 @@ struct sx_handle {
     double* d_metrics = nullptr;  // eta_y, eta_yy, y_eta  (3*ny)
     double* d_scratch = nullptr;  // reduction partials + results
     double* d_force = nullptr;    // bulk forcing: per-workgroup partial sums + force
-    // hybrid scheme (sensor on): theta, face flags, face and node lists, dF
+    // hybrid scheme (sensor on): sensor exceedance, face flags, face and node lists, dF
     sx::WenoBufs wb = {};
     unsigned long long* d_fcount = nullptr;
     int flag_override = 0;

@@ -170,7 +170,7 @@ hipError_t launch_max_rate(const KGrid& g, const KGas& gas, const double* W, dou
                            int nscratch_blocks, hipStream_t st);
 // Buffers of the hybrid (sensor + WENO) path.
 struct WenoBufs {
-    double* theta;              // sensor at interior nodes [nz][ny][nx]
+    unsigned char* sens;        // theta > threshold at interior nodes [nz][ny][nx]
     unsigned char* f[3];        // face flags per direction (n_d + 1 faces per line)
     int* flist[3];              // flagged faces per direction (face indices)
     int* nlist;                 // nodes with a flagged face (interior indices)

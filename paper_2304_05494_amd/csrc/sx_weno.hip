@@ -24,8 +24,9 @@
 // Sensor: theta = max(0, -div u / sqrt(div u^2 + |curl u|^2 + eps^2)) with
 // second-order central differences at interior nodes; a face i+1/2 uses WENO
 // iff the largest theta over the WENO stencil nodes i-r+1 .. i+r exceeds the
-// threshold; ghost nodes take theta of their periodic image, else of their
-// mirror interior node. Flags are decided in FP64 in both precision forms.
+// threshold, that is iff any of them exceeds it; ghost nodes take theta of
+// their periodic image, else of their mirror interior node. theta and its
+// comparison are FP64 in both precision forms.
 //
 // WENO flux at a face: Roe average of the two adjacent nodes, eigenvectors
 // of the Euler flux Jacobian in (rho, rho u_n, rho u_t1, rho u_t2, rho E),
@@ -48,13 +49,17 @@ __device__ __forceinline__ int map_ghost(int i, int n, int bc_lo, int bc_hi)
     return i;
 }
 
-// theta at interior nodes, stored [nz][ny][nx]. A workgroup owns a TXT x
-// TYT column tile and marches a chunk of TZT planes; velocities of three
-// planes (tile + one halo node, read from the ghosted state) sit in an LDS
-// ring, so each node's velocity is formed once.
+// theta at interior nodes, compared with the threshold once: a face's
+// flag only asks whether the largest theta of its window exceeds the
+// threshold, i.e. whether any node's does, so one byte per node (stored
+// [nz][ny][nx]) carries all the flags need. A workgroup owns a TXT x TYT
+// column tile and marches a chunk of TZT planes; velocities of three planes
+// (tile + one halo node, read from the ghosted state) sit in an LDS ring,
+// so each node's velocity is formed once.
 constexpr int TXT = 64, TYT = 8, TZT = 16;
-__global__ void __launch_bounds__(TXT * TYT) k_theta(KGrid g, double eps, const double* __restrict__ W,
-                                                     double* __restrict__ theta)
+__global__ void __launch_bounds__(TXT * TYT) k_theta(KGrid g, double eps, double thr,
+                                                     const double* __restrict__ W,
+                                                     unsigned char* __restrict__ sens)
 {
     constexpr int HXT = TXT + 2, HYT = TYT + 2, HPT = HXT * HYT;
     __shared__ double vel[3][3][HPT];   // ring slot, component, node
@@ -101,7 +106,7 @@ __global__ void __launch_bounds__(TXT * TYT) k_theta(KGrid g, double eps, const 
             const double div = ux + vy + wz;
             const double o1 = wy - vz, o2 = uz - wx, o3 = vx - uy;
             const double t = -div / sqrt(div * div + (o1 * o1 + o2 * o2 + o3 * o3) + eps * eps);
-            theta[((long long)k * g.ny + j) * g.nx + i] = t > 0.0 ? t : 0.0;
+            sens[((long long)k * g.ny + j) * g.nx + i] = (t > 0.0 ? t : 0.0) > thr;
         }
         __syncthreads();
     }
@@ -188,9 +193,9 @@ __global__ void __launch_bounds__(WB) k_lists(KGrid g, WenoBufs b)
 
 // Flags and lists in one pass (the sensor path; injected flags go through
 // k_lists). A workgroup owns a GX x GY column tile and marches a chunk of
-// GZ planes: theta of the plane with an r-wide x/y halo sits in LDS (x and
-// y maxima), each thread keeps its column's last 2r+1 theta values in
-// registers (z maxima). Every node decides all six of its faces
+// GZ planes: the sensor bytes of the plane with an r-wide x/y halo sit in
+// LDS (x and y windows), each thread keeps its column's last 2r+1 in
+// registers (z windows). Every node decides all six of its faces
 // (the "+" faces it owns and the "-" faces, whose windows it reads from the
 // same LDS plane and register window), so it knows at once which faces it
 // lists and whether it is a listed node. Those bits stay in LDS over the
@@ -200,12 +205,11 @@ __global__ void __launch_bounds__(WB) k_lists(KGrid g, WenoBufs b)
 // face of each line by the line's first node).
 constexpr int GX = 64, GY = 8, GZ = 32;
 template <int RW>
-__global__ void __launch_bounds__(GX * GY) k_flaglist(KGrid g, double thr, const double* __restrict__ theta,
-                                                      WenoBufs b)
+__global__ void __launch_bounds__(GX * GY) k_flaglist(KGrid g, const unsigned char* __restrict__ sens, WenoBufs b)
 {
     constexpr int HXF = GX + 2 * RW, HYF = GY + 2 * RW, HPF = HXF * HYF;
     constexpr int NPF = (HPF + GX * GY - 1) / (GX * GY);
-    __shared__ double pl[HYF][HXF];
+    __shared__ unsigned pl[HYF][HXF];
     __shared__ unsigned char bits[GZ][GX * GY];   // flags of the node's faces x-, x+, y-, y+, z-, z+
     __shared__ int cur[4], base[4];
     if (threadIdx.x < 4) cur[threadIdx.x] = 0;
@@ -216,7 +220,7 @@ __global__ void __launch_bounds__(GX * GY) k_flaglist(KGrid g, double thr, const
     const int k0 = blockIdx.z * GZ, k1 = min(k0 + GZ, g.nz);
     const long long psz = (long long)g.ny * g.nx;
     // in-plane offsets of this thread's halo points (x and y mapped once;
-    // ghost positions take theta of their periodic image or mirror node)
+    // ghost positions take the sensor of their periodic image or mirror node)
     // and of its own column; the plane part is uniform
     int hoff[NPF];
 #pragma unroll
@@ -226,20 +230,20 @@ __global__ void __launch_bounds__(GX * GY) k_flaglist(KGrid g, double thr, const
         hoff[a] = map_ghost(y, g.ny, g.bc[2], g.bc[3]) * g.nx + map_ghost(x, g.nx, g.bc[0], g.bc[1]);
     }
     const int coff = (active ? j : 0) * g.nx + (active ? i : 0);
-    auto plane = [&](int k) { return theta + map_ghost(k, g.nz, g.bc[4], g.bc[5]) * psz; };
-    double win[2 * RW + 1];   // theta of this column at planes k-r .. k+r
+    auto plane = [&](int k) { return sens + map_ghost(k, g.nz, g.bc[4], g.bc[5]) * psz; };
+    unsigned win[2 * RW + 1];   // sensor of this column at planes k-r .. k+r
 #pragma unroll
     for (int t = 1; t <= 2 * RW; ++t) win[t] = plane(k0 - RW - 1 + t)[coff];   // planes k0-r .. k0+r-1
-    win[0] = 0.0;
+    win[0] = 0;
     auto wave_count = [&](bool pred, int* c) {
         const unsigned long long m = __ballot(pred);
         if (m && __lane_id() == __ffsll((long long)m) - 1) atomicAdd(c, __popcll(m));
     };
-    // theta of the next plane (this thread's halo points, its column's new
+    // sensor of the next plane (this thread's halo points, its column's new
     // window value) is loaded while the current plane is decided
-    double hv[NPF], wv;
+    unsigned hv[NPF], wv;
     auto load_plane = [&](int k) {
-        const double* tp = plane(k);
+        const unsigned char* tp = plane(k);
 #pragma unroll
         for (int a = 0; a < NPF; ++a)
             if (a + 1 < NPF || threadIdx.x + a * GX * GY < HPF) hv[a] = tp[hoff[a]];
@@ -270,20 +274,16 @@ __global__ void __launch_bounds__(GX * GY) k_flaglist(KGrid g, double thr, const
         if (active) {
             const int cx = tx + RW, cy = ty + RW;
             // "+" face: nodes -r+1 .. r around the node; "-" face: -r .. r-1
-            double xp = 0.0, yp = 0.0, zp = 0.0;
+            unsigned xc = 0, yc = 0, zc = 0;
 #pragma unroll
             for (int t = -RW + 1; t <= RW - 1; ++t) {
-                xp = fmax(xp, pl[cy][cx + t]);
-                yp = fmax(yp, pl[cy + t][cx]);
+                xc |= pl[cy][cx + t];
+                yc |= pl[cy + t][cx];
             }
 #pragma unroll
-            for (int t = 1; t < 2 * RW; ++t) zp = fmax(zp, win[t]);
-            const double xm = fmax(pl[cy][cx - RW], xp), ym = fmax(pl[cy - RW][cx], yp), zm = fmax(win[0], zp);
-            xp = fmax(xp, pl[cy][cx + RW]);
-            yp = fmax(yp, pl[cy + RW][cx]);
-            zp = fmax(zp, win[2 * RW]);
-            const bool fxp = xp > thr, fxm = xm > thr, fyp = yp > thr, fym = ym > thr;
-            const bool fzp = zp > thr, fzm = zm > thr;
+            for (int t = 1; t < 2 * RW; ++t) zc |= win[t];
+            const bool fxm = xc | pl[cy][cx - RW], fym = yc | pl[cy - RW][cx], fzm = zc | win[0];
+            const bool fxp = xc | pl[cy][cx + RW], fyp = yc | pl[cy + RW][cx], fzp = zc | win[2 * RW];
             unsigned char* const fx = b.f[0] + k * fxk;
             unsigned char* const fy = b.f[1] + k * fyk;
             unsigned char* const fz = b.f[2] + k * psz;
@@ -332,10 +332,10 @@ __global__ void __launch_bounds__(GX * GY) k_flaglist(KGrid g, double thr, const
 }
 
 template <int RW>
-static void launch_flaglist(const KGrid& g, double thr, const WenoBufs& b, hipStream_t st)
+static void launch_flaglist(const KGrid& g, const WenoBufs& b, hipStream_t st)
 {
     const dim3 grid((unsigned)((g.nx + GX - 1) / GX), (unsigned)((g.ny + GY - 1) / GY), (unsigned)((g.nz + GZ - 1) / GZ));
-    hipLaunchKernelGGL(k_flaglist<RW>, grid, dim3(GX * GY), 0, st, g, thr, b.theta, b);
+    hipLaunchKernelGGL(k_flaglist<RW>, grid, dim3(GX * GY), 0, st, g, b.sens, b);
 }
 
 __global__ void k_zero_counts(int* p)
@@ -717,12 +717,12 @@ hipError_t launch_sensor_flags(const KGrid& g, const KScheme& sc, const double* 
     if (!use_override) {
         const dim3 tgrid((unsigned)((g.nx + TXT - 1) / TXT), (unsigned)((g.ny + TYT - 1) / TYT),
                          (unsigned)((g.nz + TZT - 1) / TZT));
-        hipLaunchKernelGGL(k_theta, tgrid, dim3(TXT * TYT), 0, st, g, sc.sensor_eps, W, b.theta);
+        hipLaunchKernelGGL(k_theta, tgrid, dim3(TXT * TYT), 0, st, g, sc.sensor_eps, sc.sensor_thr, W, b.sens);
         switch (sc.r) {
-        case 1: launch_flaglist<1>(g, sc.sensor_thr, b, st); break;
-        case 2: launch_flaglist<2>(g, sc.sensor_thr, b, st); break;
-        case 3: launch_flaglist<3>(g, sc.sensor_thr, b, st); break;
-        default: launch_flaglist<4>(g, sc.sensor_thr, b, st); break;
+        case 1: launch_flaglist<1>(g, b, st); break;
+        case 2: launch_flaglist<2>(g, b, st); break;
+        case 3: launch_flaglist<3>(g, b, st); break;
+        default: launch_flaglist<4>(g, b, st); break;
         }
         return hipGetLastError();
     }
