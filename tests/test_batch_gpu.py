@@ -82,6 +82,28 @@ def test_batch_matches_oracle_after_ten_steps():
         assert np.all(err < 1e-12), (b, err)
 
 
+def test_batch_fp32_flux_matches_oracle_after_ten_steps():
+    """The batched FP32-flux form against the FP64 oracle: each block's
+    state after 10 RK3 steps within the FP32-flux bound of the single-block
+    form (relative 1e-5 per field; the FP32 rounding of the stencil sums,
+    far above the FP64 path's 1e-12)."""
+    cases = [small_batch()[0], small_batch()[3]]
+    bh, fields = make_batch(cases, sx.SX_FP32_FLUX)
+    dt = min(oracle_for(c).compute_dt(f.copy(), 0.5) for c, f in zip(cases, fields))
+    for _ in range(10):
+        bh.sx_rk3_step(dt)
+    torch.cuda.synchronize()
+    for b, c in enumerate(cases):
+        o = oracle_for(c)
+        Wo = fields[b].copy()
+        Rp = np.zeros((5, c.nz, c.ny, c.nx))
+        for _ in range(10):
+            o.rk3_step(Wo, Rp, dt)
+        err = rel_err_per_field(bh.box_interior(bh.state, b), o.interior(Wo))
+        assert np.all(err < 1e-5), (b, err)
+        assert np.any(err > 1e-12), (b, err)   # it does run in FP32
+
+
 def test_graph_replay_equals_direct_launches():
     cases = small_batch()
     ga, fields = make_batch(cases)
