@@ -172,6 +172,8 @@ void sx_fill_kernel_params(const sx_grid& g, const sx_gas& gas, const sx_scheme&
     kg->dxi = 1.0 / kg->dx;
     kg->dzi = 1.0 / kg->dz;
     kg->fpart = nullptr;
+    kg->sens = nullptr;
+    kg->sens_eps = kg->sens_thr = 0.0;
 
     kgas->gamma = gas.gamma;
     kgas->gm1 = gas.gamma - 1.0;
@@ -373,7 +375,7 @@ int sx_rhs(sx_handle* h, double* W, double* R, unsigned term_mask)
     if (e == hipSuccess)
         e = sx::launch_rhs(h->kg, h->kgas, h->ks, W, R, nullptr, nullptr, term_mask, false, h->st);
     if (e == hipSuccess && h->ks.sensor && (term_mask & (SX_CONV_X | SX_CONV_Y | SX_CONV_Z))) {
-        e = sx::launch_sensor_flags(h->kg, h->ks, W, h->wb, h->flag_override, h->st);
+        e = sx::launch_sensor_flags(h->kg, h->ks, W, h->wb, h->flag_override, 0, h->st);
         if (e == hipSuccess)
             e = sx::launch_weno(h->kg, h->kgas, h->ks, term_mask, W, h->wb, 0, 0.0, 0, R, nullptr, h->st);
     }
@@ -391,6 +393,17 @@ int sx_rk3_step(sx_handle* h, double dt)
     if (!h->bound) return sx_fail(h, SX_ESTATE, "sx_rk3_step: no buffers bound");
     if (!(dt > 0.0) || !isfinite(dt)) return sx_fail(h, SX_EINVAL, "sx_rk3_step: dt must be positive");
     if (h->batch) return sx_batch_step(h, dt);
+    // hybrid step on the FP64 default scheme: the fused kernel evaluates the
+    // sensor of its input state on the way (it holds every plane's
+    // velocities), so the separate sensor pass is skipped
+    const bool fused_sensor = h->ks.sensor && !h->flag_override && !h->pimg && h->ks.precision == SX_FP64 &&
+                              h->ks.flux != SX_FLUX_KEEP && !h->kgas.thermo;
+    sx::KGrid kgs = h->kg;
+    if (fused_sensor) {
+        kgs.sens = h->wb.sens;
+        kgs.sens_eps = h->ks.sensor_eps;
+        kgs.sens_thr = h->ks.sensor_thr;
+    }
     for (int s = 0; s < 3; ++s) {
         double* src = h->W[h->cur];
         double* dst = h->W[1 - h->cur];
@@ -400,10 +413,10 @@ int sx_rk3_step(sx_handle* h, double dt)
         std::pair<hipEvent_t, hipEvent_t> ev{};
         if (e == hipSuccess && h->timing) e = sx_timed_begin(h, &ev);
         if (e == hipSuccess)
-            e = sx::launch_rhs(h->kg, h->kgas, h->ks, src, dst, h->Rprev, &sc, SX_ALL, h->pimg, h->st);
+            e = sx::launch_rhs(kgs, h->kgas, h->ks, src, dst, h->Rprev, &sc, SX_ALL, h->pimg, h->st);
         if (e == hipSuccess && h->timing) e = sx_timed_end(h, ev);
         if (e == hipSuccess && h->ks.sensor) {
-            e = sx::launch_sensor_flags(h->kg, h->ks, src, h->wb, h->flag_override, h->st);
+            e = sx::launch_sensor_flags(h->kg, h->ks, src, h->wb, h->flag_override, fused_sensor, h->st);
             if (e == hipSuccess)
                 e = sx::launch_weno(h->kg, h->kgas, h->ks, SX_ALL, src, h->wb, 1, sc.cg, sc.write_prev,
                                     dst, h->Rprev, h->st);
@@ -453,7 +466,7 @@ int sx_diagnostics(sx_handle* h, const double* R, sx_diag* out)
             double* Wc = h->W[h->cur];
             e = sx::launch_ghost_fill(h->kg, h->kgas, Wc, h->st);
             if (e == hipSuccess)
-                e = sx::launch_sensor_flags(h->kg, h->ks, Wc, h->wb, h->flag_override, h->st);
+                e = sx::launch_sensor_flags(h->kg, h->ks, Wc, h->wb, h->flag_override, 0, h->st);
             if (e == hipSuccess)
                 e = sx::launch_count_flags(h->kg, h->wb.f[0], h->wb.f[1], h->wb.f[2], h->d_fcount, h->st);
             if (e == hipSuccess)

@@ -23,6 +23,8 @@ struct KGrid {
     const double* eta_yy;       // [ny] -y_etaeta / y_eta^3
     const double* y_eta;        // [ny]
     double* fpart;              // bulk forcing: one partial sum per workgroup (nullptr: off)
+    unsigned char* sens;        // hybrid step: sensor bytes written by the fused kernel (nullptr: off)
+    double sens_eps, sens_thr;  // sensor epsilon and threshold
 };
 
 struct KGas {
@@ -179,8 +181,9 @@ struct WenoBufs {
     int* counts;                // list lengths: faces x, y, z, nodes
     double* dF[3];              // WENO minus central flux per face, [5][faces_d]
 };
+// sens_done: the sensor bytes were written by the fused kernel of this substep
 hipError_t launch_sensor_flags(const KGrid& g, const KScheme& sc, const double* W,
-                               const WenoBufs& b, int use_override, hipStream_t st);
+                               const WenoBufs& b, int use_override, int sens_done, hipStream_t st);
 hipError_t launch_weno(const KGrid& g, const KGas& gas, const KScheme& sc, unsigned mask,
                        const double* W, const WenoBufs& b, int mode, double cg, int write_prev,
                        double* out, double* Rp, hipStream_t st);

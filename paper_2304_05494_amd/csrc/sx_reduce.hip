@@ -305,7 +305,7 @@ extern "C" int sx_diagnostics_noalloc(sx_handle* h, const double* R, double* out
             double* Wc = h->W[h->cur];
             e = sx::launch_ghost_fill(h->kg, h->kgas, Wc, h->st);
             if (e == hipSuccess)
-                e = sx::launch_sensor_flags(h->kg, h->ks, Wc, h->wb, h->flag_override, h->st);
+                e = sx::launch_sensor_flags(h->kg, h->ks, Wc, h->wb, h->flag_override, 0, h->st);
             if (e == hipSuccess)
                 e = sx::launch_count_flags(h->kg, h->wb.f[0], h->wb.f[1], h->wb.f[2], fc, h->st);
         }

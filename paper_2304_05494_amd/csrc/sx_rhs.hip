@@ -328,10 +328,13 @@ __device__ __forceinline__ void keep_pair(const Node<double>& A, const Node<doub
     F[4] = frho * K + 0.5 * (A.p * udB + B.p * udA);
 }
 
-template <int SC, int SV, int D, bool CONV, bool VISC, bool KEEP = false, typename R, typename Get>
+template <int SC, int SV, int D, bool CONV, bool VISC, bool KEEP = false, bool D1 = false, typename R,
+          typename Get>
 __device__ __forceinline__ void stencil_dir(Get get, R sc, R sc2, R scy, R (&acc)[NV], R (&gd)[4],
                                             R (&dd)[4], const KGas* kgas = nullptr)
 {
+    // D1 (convective only): gd[0..2] return the differences u, v, w of the
+    // two nodes at distance 1, for the second-order sensor
     // convective pairs up to SC, viscous differences up to SV
     constexpr int SL = CONV && VISC ? Halo<SC, SV>::S : (CONV ? SC : SV);
     const Node<R> C = get(0);
@@ -340,6 +343,13 @@ __device__ __forceinline__ void stencil_dir(Get get, R sc, R sc2, R scy, R (&acc
 #pragma unroll
     for (int l = 1; l <= SL; ++l) {
         const Node<R> M = get(-l), P = get(l);
+        if constexpr (D1 && !VISC) {
+            if (l == 1) {
+                gd[0] = P.u - M.u;
+                gd[1] = P.v - M.v;
+                gd[2] = P.w - M.w;
+            }
+        }
         if constexpr (KEEP) {
             if (CONV && l <= SC) {
                 // F(C, P) - F(M, C) with the KEEP-n pair flux
@@ -1337,7 +1347,9 @@ __device__ __forceinline__ void march_ring(SmemRing<Halo<SC, SV>::S, TX, TY>& sm
     using R = double;
     const unsigned mask = UPD ? (unsigned)SX_ALL : mask_in;
     constexpr int S = Halo<SC, SV>::S;
-    constexpr bool KEEP = VAR == 1, THERMO = VAR == 2;
+    // variants: 1 KEEP-n central flux, 2 thermally perfect gas, 3 the default
+    // scheme plus the Ducros sensor of the hybrid step
+    constexpr bool KEEP = VAR == 1, THERMO = VAR == 2, SENS = VAR == 3;
     constexpr int NR = TX * TY;
     constexpr int HX = TX + 2 * S, HP = HX * (TY + 2 * S);
     constexpr int NPT = (HP + 2 * NR - 1) / (2 * NR);   // staged points per thread (both roles)
@@ -1601,12 +1613,34 @@ __device__ __forceinline__ void march_ring(SmemRing<Halo<SC, SV>::S, TX, TY>& sm
                 acc[2] += myx;
                 acc[4] += Cc.u * mxy + Cc.v * myx;
             }
-            if (active) {
+            if (!SENS && active) {
                 R gd[4], dd[4];
                 auto gz_ = [&](int t) { return znode_at(k, t); };
                 if (mask & SX_CONV_X) stencil_dir<SC, SV, 0, true, false, KEEP>(gx_, dxi, dxi, R(0), acc, gd, dd, &gas);
                 if (mask & SX_CONV_Y) stencil_dir<SC, SV, 1, true, false, KEEP>(gy_, ey, ey, R(0), acc, gd, dd, &gas);
                 if (mask & SX_CONV_Z) stencil_dir<SC, SV, 2, true, false, KEEP>(gz_, dzi, dzi, R(0), acc, gd, dd, &gas);
+            }
+            if constexpr (SENS) {
+                // the Ducros sensor of the input state at this node, from the
+                // second-order differences of the velocities the convective
+                // stencils load anyway, compared with the threshold: one byte
+                // per node for the face flags
+                if (active) {
+                    R dx[4], dy[4], dz[4], dd[4];
+                    stencil_dir<SC, SV, 0, true, false, false, true>(gx_, dxi, dxi, R(0), acc, dx, dd);
+                    stencil_dir<SC, SV, 1, true, false, false, true>(gy_, ey, ey, R(0), acc, dy, dd);
+                    auto gz_ = [&](int t) { return znode_at(k, t); };
+                    stencil_dir<SC, SV, 2, true, false, false, true>(gz_, dzi, dzi, R(0), acc, dz, dd);
+                    const double ix = 0.5 * g.dxi, iy = 0.5 * g.eta_y[j], iz = 0.5 * g.dzi;
+                    const double ux = dx[0] * ix, vx = dx[1] * ix, wx = dx[2] * ix;
+                    const double uy = dy[0] * iy, vy = dy[1] * iy, wy = dy[2] * iy;
+                    const double uz = dz[0] * iz, vz = dz[1] * iz, wz = dz[2] * iz;
+                    const double div = ux + vy + wz;
+                    const double o1 = wy - vz, o2 = uz - wx, o3 = vx - uy;
+                    const double eps = g.sens_eps;
+                    const double t = -div / sqrt(div * div + (o1 * o1 + o2 * o2 + o3 * o3) + eps * eps);
+                    g.sens[((long long)k * g.ny + j) * g.nx + i] = (t > 0.0 ? t : 0.0) > g.sens_thr;
+                }
             }
             __syncthreads();                                   // 2: viscous part ready
             if (active) {
@@ -1961,6 +1995,21 @@ static hipError_t launch_rhs_SR(const KGrid& g, const KGas& gas, const double* W
             else
                 hipLaunchKernelGGL((k_rhs_central<SC, SV, TX, TY, WPE, R, false, false, SP, 2>), grid,
                                    dim3(NTH), 0, st, W, out, Rprev, g, gas, none, mask, kc);
+            hipError_t e = hipGetLastError();
+            if (e == hipSuccess && force) e = launch_force(g, nwg, W, out, Rprev, step, st);
+            return e;
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
+    if (g.sens) {
+        // hybrid step: the fused kernel also writes the sensor bytes (FP64
+        // plane-ring march, update mode, no periodic images; the handle
+        // selects it only then)
+        if constexpr (RingOf<S, TX, TY, R, SP>::value) {
+            if (!step || pimg || var != 0) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_rhs_central<SC, SV, TX, TY, WPE, R, true, false, SP, 3>), grid, dim3(NTH), 0, st,
+                               W, out, Rprev, g, gas, *step, (unsigned)SX_ALL, kc);
             hipError_t e = hipGetLastError();
             if (e == hipSuccess && force) e = launch_force(g, nwg, W, out, Rprev, step, st);
             return e;

@@ -710,14 +710,15 @@ hipError_t launch_count_flags(const KGrid& g, const unsigned char* fx, const uns
 }
 
 hipError_t launch_sensor_flags(const KGrid& g, const KScheme& sc, const double* W,
-                               const WenoBufs& b, int use_override, hipStream_t st)
+                               const WenoBufs& b, int use_override, int sens_done, hipStream_t st)
 {
     const dim3 grid((unsigned)((g.nint + WB - 1) / WB));
     hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(64), 0, st, b.counts);
     if (!use_override) {
         const dim3 tgrid((unsigned)((g.nx + TXT - 1) / TXT), (unsigned)((g.ny + TYT - 1) / TYT),
                          (unsigned)((g.nz + TZT - 1) / TZT));
-        hipLaunchKernelGGL(k_theta, tgrid, dim3(TXT * TYT), 0, st, g, sc.sensor_eps, sc.sensor_thr, W, b.sens);
+        if (!sens_done)
+            hipLaunchKernelGGL(k_theta, tgrid, dim3(TXT * TYT), 0, st, g, sc.sensor_eps, sc.sensor_thr, W, b.sens);
         switch (sc.r) {
         case 1: launch_flaglist<1>(g, b, st); break;
         case 2: launch_flaglist<2>(g, b, st); break;
