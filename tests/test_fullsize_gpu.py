@@ -100,6 +100,13 @@ def test_shock_bl_full_size_flags_and_10_steps():
     print("initial flags: fractions", [float(f.mean()) for f in ref0], "mismatches", mis0, flush=True)
     assert all(0.02 < f.mean() < 0.3 for f in ref0)
     assert mis0 == [0, 0, 0]
+    # the fused sensor of the RK3 step on the same state: a 1e-300 step
+    # moves the state by ~1e-300 at most and leaves its flags behind
+    h.sx_rk3_step(1e-300)
+    torch.cuda.synchronize()
+    misf = _flag_mismatch(h.sx_get_flags(), ref0)
+    print("fused-sensor flags: mismatches", misf, flush=True)
+    assert misf == [0, 0, 0]
     for _ in range(10):
         h.sx_rk3_step(dt)
     d = h.sx_diagnostics()                 # sensor on the final state

@@ -104,6 +104,33 @@ def test_hybrid_rk3_steps_parity():
     assert np.all(err < 1e-12), err
 
 
+def test_fused_sensor_flags_match_oracle():
+    """In an FP64 RK3 step the fused kernel evaluates the sensor of each
+    substep's input state. A step of 1e-300 changes the state by at most
+    1e-300 times its right-hand side (nonzero components stay bitwise, zero
+    ones move by ~1e-300), so the flags the step leaves behind are the fused
+    sensor's flags of the initial state: element-wise equal to the oracle's,
+    and to those of the separate sensor pass (sx_rhs)."""
+    case = SBL
+    Wn = np.ascontiguousarray(inputs.fields(case))
+    ref = oracle_for(case).face_flags(Wn.copy())
+    h = sx.Handle(case)
+    W = h.to_layout(Wn)
+    h.sx_bind(W)
+    R = h.sx_rhs(W)
+    torch.cuda.synchronize()
+    del R
+    sep = h.sx_get_flags()
+    h.sx_rk3_step(1e-300)
+    torch.cuda.synchronize()
+    assert np.abs(h.interior(h.state) - h.interior(h.to_layout(Wn))).max() < 1e-290
+    fused = h.sx_get_flags()
+    for d in range(3):
+        assert ref[d].any()
+        assert np.array_equal(fused[d], ref[d]), d
+        assert np.array_equal(sep[d], ref[d]), d
+
+
 def test_hybrid_determinism():
     case = SBL
     o = oracle_for(case)
