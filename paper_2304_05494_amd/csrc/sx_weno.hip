@@ -373,8 +373,16 @@ __device__ __forceinline__ R weno7_left(const R* v, R eps)
         const R P3 = d3 * R(1.0 / 6.0);
         q[k] = v[3] + R(0.5) * P1 + P2 * R(1.0 / 6.0);
         const R b = P1 * P1 + R(13.0 / 3.0) * P2 * P2 + R(781.0 / 20.0) * P3 * P3;
-        a[k] = dw[k] / ((eps + b) * (eps + b));
+        a[k] = (eps + b) * (eps + b);   // s_k^2
     }
+    if constexpr (std::is_same<R, double>::value) {
+        // d_k / s_k^2 times the product of all s_j^2: one division
+        const R s01 = a[0] * a[1], s23 = a[2] * a[3];
+        const R w0 = dw[0] * (a[1] * s23), w1 = dw[1] * (a[0] * s23), w2 = dw[2] * (s01 * a[3]), w3 = dw[3] * (s01 * a[2]);
+        return (w0 * q[0] + w1 * q[1] + w2 * q[2] + w3 * q[3]) / (w0 + w1 + w2 + w3);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a[k] = dw[k] / a[k];
     return (a[0] * q[0] + a[1] * q[1] + a[2] * q[2] + a[3] * q[3]) / (a[0] + a[1] + a[2] + a[3]);
 }
 
@@ -388,6 +396,12 @@ __device__ __forceinline__ R weno_left(const R* v, R eps)
         const R vm = v[0], v0 = v[1], vp = v[2];
         const R q0 = R(0.5) * (-vm + R(3) * v0), q1 = R(0.5) * (v0 + vp);
         const R b0 = (v0 - vm) * (v0 - vm), b1 = (vp - v0) * (vp - v0);
+        if constexpr (std::is_same<R, double>::value) {
+            // weights d_k / s_k^2 scaled by the product of all s_j^2: one division
+            const R p0 = (eps + b0) * (eps + b0), p1 = (eps + b1) * (eps + b1);
+            const R a0 = R(1.0 / 3.0) * p1, a1 = R(2.0 / 3.0) * p0;
+            return (a0 * q0 + a1 * q1) / (a0 + a1);
+        }
         const R a0 = R(1.0 / 3.0) / ((eps + b0) * (eps + b0));
         const R a1 = R(2.0 / 3.0) / ((eps + b1) * (eps + b1));
         return (a0 * q0 + a1 * q1) / (a0 + a1);
@@ -403,6 +417,15 @@ __device__ __forceinline__ R weno_left(const R* v, R eps)
     t = vm - vp; b1 += R(0.25) * t * t;
     t = v0 - R(2) * vp + vpp; b2 = R(13.0 / 12.0) * t * t;
     t = R(3) * v0 - R(4) * vp + vpp; b2 += R(0.25) * t * t;
+    if constexpr (std::is_same<R, double>::value) {
+        // the nonlinear weights d_k / s_k^2 (s_k = eps + beta_k) times the
+        // product of all s_j^2, so a single division normalises them (FP64
+        // range: with eps = 1e-6 the products stay far from under- and
+        // overflow)
+        const R p0 = (eps + b0) * (eps + b0), p1 = (eps + b1) * (eps + b1), p2 = (eps + b2) * (eps + b2);
+        const R a0 = R(0.1) * (p1 * p2), a1 = R(0.6) * (p0 * p2), a2 = R(0.3) * (p0 * p1);
+        return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+    }
     const R a0 = R(0.1) / ((eps + b0) * (eps + b0));
     const R a1 = R(0.6) / ((eps + b1) * (eps + b1));
     const R a2 = R(0.3) / ((eps + b2) * (eps + b2));
