@@ -447,7 +447,13 @@ __device__ __forceinline__ void face_delta(const double* __restrict__ W, long lo
                                            long long sv, const KGas& gas, R eps, double (&dF)[NV])
 {
     constexpr int perm[NV] = {0, 1 + d, 1 + (d + 1) % 3, 1 + (d + 2) % 3, 4};
+    constexpr int NS = 2 * RW;          // WENO stencil nodes
+    constexpr int OFF = HALF - RW;      // first WENO node in nd[]
+    constexpr bool F64 = std::is_same<R, double>::value;
     FNode<R> nd[2 * HALF];
+    // local Lax-Friedrichs speeds: largest |u_n - c|, |u_n|, |u_n + c| over
+    // the WENO stencil (FP64: taken while the nodes load, c from 1/rho)
+    R lm = R(0), l0 = R(0), lp = R(0);
 #pragma unroll
     for (int q = 0; q < 2 * HALF; ++q) {
         double w5[NV];
@@ -465,6 +471,14 @@ __device__ __forceinline__ void face_delta(const double* __restrict__ W, long lo
         f.w = R(w);
         f.p = R(p);
         f.H = R((w5[4] + p) * ri);
+        if constexpr (F64) {
+            if (q >= OFF && q < OFF + NS) {
+                const double unt = w5[perm[1]] * ri, ct = sqrt(gas.gamma * p * ri);
+                lm = fmax(lm, fabs(unt - ct));
+                l0 = fmax(l0, fabs(unt));
+                lp = fmax(lp, fabs(unt + ct));
+            }
+        }
     }
     auto vel = [&](const FNode<R>& q, int c) { return c == 0 ? q.u : (c == 1 ? q.v : q.w); };
 
@@ -513,18 +527,16 @@ __device__ __forceinline__ void face_delta(const double* __restrict__ W, long lo
         }
     };
 
-    constexpr int NS = 2 * RW;          // WENO stencil nodes
-    constexpr int OFF = HALF - RW;      // first WENO node in nd[]
-    // local Lax-Friedrichs speeds: largest |u_n - c|, |u_n|, |u_n + c| over the stencil
-    R lm = R(0), l0 = R(0), lp = R(0);
+    if constexpr (!F64) {
 #pragma unroll
-    for (int t = 0; t < NS; ++t) {
-        const FNode<R>& n = nd[OFF + t];
-        const R unt = vel(n, d);
-        const R ct = sqrt(R(gas.gamma) * n.p / n.r);
-        lm = fmax(lm, fabs(unt - ct));
-        l0 = fmax(l0, fabs(unt));
-        lp = fmax(lp, fabs(unt + ct));
+        for (int t = 0; t < NS; ++t) {
+            const FNode<R>& n = nd[OFF + t];
+            const R unt = vel(n, d);
+            const R ct = sqrt(R(gas.gamma) * n.p / n.r);
+            lm = fmax(lm, fabs(unt - ct));
+            l0 = fmax(l0, fabs(unt));
+            lp = fmax(lp, fabs(unt + ct));
+        }
     }
     R Fh[NV];
 #pragma unroll
