@@ -396,14 +396,9 @@ __device__ __forceinline__ R weno_left(const R* v, R eps)
         const R vm = v[0], v0 = v[1], vp = v[2];
         const R q0 = R(0.5) * (-vm + R(3) * v0), q1 = R(0.5) * (v0 + vp);
         const R b0 = (v0 - vm) * (v0 - vm), b1 = (vp - v0) * (vp - v0);
-        if constexpr (std::is_same<R, double>::value) {
-            // weights d_k / s_k^2 scaled by the product of all s_j^2: one division
-            const R p0 = (eps + b0) * (eps + b0), p1 = (eps + b1) * (eps + b1);
-            const R a0 = R(1.0 / 3.0) * p1, a1 = R(2.0 / 3.0) * p0;
-            return (a0 * q0 + a1 * q1) / (a0 + a1);
-        }
-        const R a0 = R(1.0 / 3.0) / ((eps + b0) * (eps + b0));
-        const R a1 = R(2.0 / 3.0) / ((eps + b1) * (eps + b1));
+        // weights d_k / s_k^2 times the other s_j^2: one division
+        const R p0 = (eps + b0) * (eps + b0), p1 = (eps + b1) * (eps + b1);
+        const R a0 = R(1.0 / 3.0) * p1, a1 = R(2.0 / 3.0) * p0;
         return (a0 * q0 + a1 * q1) / (a0 + a1);
     }
     const R vmm = v[0], vm = v[1], v0 = v[2], vp = v[3], vpp = v[4];
@@ -417,18 +412,12 @@ __device__ __forceinline__ R weno_left(const R* v, R eps)
     t = vm - vp; b1 += R(0.25) * t * t;
     t = v0 - R(2) * vp + vpp; b2 = R(13.0 / 12.0) * t * t;
     t = R(3) * v0 - R(4) * vp + vpp; b2 += R(0.25) * t * t;
-    if constexpr (std::is_same<R, double>::value) {
-        // the nonlinear weights d_k / s_k^2 (s_k = eps + beta_k) times the
-        // product of all s_j^2, so a single division normalises them (FP64
-        // range: with eps = 1e-6 the products stay far from under- and
-        // overflow)
-        const R p0 = (eps + b0) * (eps + b0), p1 = (eps + b1) * (eps + b1), p2 = (eps + b2) * (eps + b2);
-        const R a0 = R(0.1) * (p1 * p2), a1 = R(0.6) * (p0 * p2), a2 = R(0.3) * (p0 * p1);
-        return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
-    }
-    const R a0 = R(0.1) / ((eps + b0) * (eps + b0));
-    const R a1 = R(0.6) / ((eps + b1) * (eps + b1));
-    const R a2 = R(0.3) / ((eps + b2) * (eps + b2));
+    // the nonlinear weights d_k / s_k^2 (s_k = eps + beta_k) times the
+    // product of the other s_j^2, so a single division normalises them
+    // (products of two squares: with eps = 1e-6 they stay within the range
+    // of FP32 as of FP64)
+    const R p0 = (eps + b0) * (eps + b0), p1 = (eps + b1) * (eps + b1), p2 = (eps + b2) * (eps + b2);
+    const R a0 = R(0.1) * (p1 * p2), a1 = R(0.6) * (p0 * p2), a2 = R(0.3) * (p0 * p1);
     return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
 }
 
