@@ -1773,16 +1773,30 @@ k_rhs_central(const double* __restrict__ W, double* __restrict__ out, double* __
 {
     using RO = RingOf<Halo<SC, SV>::S, TX, TY, R, SPLIT>;
     __shared__ typename RO::type sm;
-    const int k0 = blockIdx.z * kc;
+    // XCD-aware tile numbering: the hardware deals workgroup b to XCD b % 8,
+    // each XCD with its own L2; XCD x takes the x-th eighth of the tiles in
+    // x-fastest order, so the tiles marching side by side on one XCD are
+    // neighbours and share their halo columns in its L2 (HBM reads of the
+    // channel launch 4.84 -> 3.35 GB)
+    int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+    const int ntl = gridDim.x * gridDim.y * gridDim.z;
+    if (ntl % 8 == 0) {
+        const int b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+        const int l = (b % 8) * (ntl / 8) + b / 8;
+        bx = l % gridDim.x;
+        by = (l / gridDim.x) % gridDim.y;
+        bz = l / (gridDim.x * gridDim.y);
+    }
+    const int k0 = bz * kc;
     if constexpr (RO::value)
-        march_ring<SC, SV, TX, TY, UPD, PIMG, VAR>(sm, W, out, Rp, g, gas, sc, mask, blockIdx.x * TX,
-                                                   blockIdx.y * TY, k0, min(k0 + kc, g.nz));
+        march_ring<SC, SV, TX, TY, UPD, PIMG, VAR>(sm, W, out, Rp, g, gas, sc, mask, bx * TX, by * TY, k0,
+                                                   min(k0 + kc, g.nz));
     else if constexpr (SPLIT)
-        march_split<SC, SV, TX, TY, R, UPD, PIMG, VAR>(sm, W, out, Rp, g, gas, sc, mask, blockIdx.x * TX,
-                                                       blockIdx.y * TY, k0, min(k0 + kc, g.nz));
+        march_split<SC, SV, TX, TY, R, UPD, PIMG, VAR>(sm, W, out, Rp, g, gas, sc, mask, bx * TX, by * TY, k0,
+                                                       min(k0 + kc, g.nz));
     else
-        march<SC, SV, TX, TY, R, UPD, PIMG, VAR>(sm, W, out, Rp, g, gas, sc, mask, blockIdx.x * TX,
-                                                 blockIdx.y * TY, k0, min(k0 + kc, g.nz));
+        march<SC, SV, TX, TY, R, UPD, PIMG, VAR>(sm, W, out, Rp, g, gas, sc, mask, bx * TX, by * TY, k0,
+                                                 min(k0 + kc, g.nz));
 }
 
 // Persistent batched kernel: each workgroup pulls (box, column tile,
