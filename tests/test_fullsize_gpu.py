@@ -37,14 +37,25 @@ def _run_gpu(case, Wn, dt, steps, precision=sx.SX_FP64):
     return h
 
 
-def _run_oracle(case, Wn, dt, steps):
+@pytest.fixture
+def progress(capsys):
+    """Progress lines written past pytest's output capture: the oracle runs
+    of these tests take minutes, and a run that stays silent that long
+    looks hung."""
+    def say(msg):
+        with capsys.disabled():
+            print(msg, flush=True)
+    return say
+
+
+def _run_oracle(case, Wn, dt, steps, say=print):
     o = oracle_for(case)
     Wo = Wn.copy()
     Rp = np.zeros((5, case.nz, case.ny, case.nx))
     for s in range(steps):
         o.rk3_step(Wo, Rp, dt)
         if (s + 1) % 5 == 0:
-            print(f"  oracle step {s + 1}/{steps}", flush=True)
+            say(f"  oracle step {s + 1}/{steps}")
     return o, Wo
 
 
@@ -60,7 +71,7 @@ def _l2_linf(a, b):
 
 
 @pytest.mark.timeout(900)
-def test_channel_full_size_10_steps():
+def test_channel_full_size_10_steps(progress):
     case = inputs.channel_case()
     print(f"channel {case.nx}x{case.ny}x{case.nz}, 10 RK3 steps", flush=True)
     Wn = np.ascontiguousarray(inputs.fields(case))
@@ -69,7 +80,7 @@ def test_channel_full_size_10_steps():
     got = h.interior(h.state)
     del h
     torch.cuda.empty_cache()
-    o, Wo = _run_oracle(case, Wn, dt, 10)
+    o, Wo = _run_oracle(case, Wn, dt, 10, progress)
     ref = o.interior(Wo)
     err = rel_err_per_field(got, ref)
     print("max rel err per field", err, flush=True)
@@ -82,7 +93,7 @@ def _flag_mismatch(got, ref):
 
 
 @pytest.mark.timeout(900)
-def test_shock_bl_full_size_flags_and_10_steps():
+def test_shock_bl_full_size_flags_and_10_steps(progress):
     case = inputs.shock_bl_case()
     print(f"shock/boundary layer {case.nx}x{case.ny}x{case.nz}, flags + 10 hybrid RK3 steps", flush=True)
     Wn = np.ascontiguousarray(inputs.fields(case))
@@ -115,7 +126,7 @@ def test_shock_bl_full_size_flags_and_10_steps():
     got = h.interior(h.state)
     del h, W
     torch.cuda.empty_cache()
-    o, Wo = _run_oracle(case, Wn, dt, 10)
+    o, Wo = _run_oracle(case, Wn, dt, 10, progress)
     ref = o.interior(Wo)
     err = rel_err_per_field(got, ref)
     print("max rel err per field", err, flush=True)
@@ -127,7 +138,7 @@ def test_shock_bl_full_size_flags_and_10_steps():
 
 
 @pytest.mark.timeout(1100)
-def test_fp32_flux_full_size_100_steps_vs_oracle():
+def test_fp32_flux_full_size_100_steps_vs_oracle(progress):
     case = inputs.channel_case()
     print(f"channel {case.nx}x{case.ny}x{case.nz}, FP32-flux form, 100 RK3 steps", flush=True)
     Wn = np.ascontiguousarray(inputs.fields(case))
@@ -138,7 +149,7 @@ def test_fp32_flux_full_size_100_steps_vs_oracle():
         res[prec] = h.interior(h.state)
         del h
         torch.cuda.empty_cache()
-    o, Wo = _run_oracle(case, Wn, dt, 100)
+    o, Wo = _run_oracle(case, Wn, dt, 100, progress)
     ref = o.interior(Wo)
     e32 = _l2_linf(res[sx.SX_FP32_FLUX], ref)
     e64 = rel_err_per_field(res[sx.SX_FP64], ref)
