@@ -1332,12 +1332,13 @@ struct SmemRing {
 //
 // Per plane: (A) stage plane k+S (all threads), role 0 stores plane k-1 and
 // role 1 evaluates the viscosity of plane k from its column record; barrier
-// 1; (B) both roles issue the loads of plane k+S+1, role 1 forms the
-// in-plane derivatives of plane k+S and the viscous terms, role 0 the
-// convective and mixed x-y terms; barrier 2 (viscous hand-over); role 0
-// completes the update. Every slot written in (A) of plane k+1 (halo slot of
-// plane k, past slot of plane k-S) was last read before barrier 2 of plane
-// k.
+// 1; (B) role 0 issues its loads of plane k+S+1 (and the next centre) and
+// evaluates the convective and mixed x-y terms (with VAR 3 also the sensor
+// byte); role 1 forms the in-plane derivatives of plane k+S and the x
+// viscous stencil, then issues its loads of plane k+S+1, then the remaining
+// viscous terms; barrier 2 (viscous hand-over); role 0 completes the update.
+// Every slot written in (A) of plane k+1 (halo slot of plane k, past slot of
+// plane k-S) was last read before barrier 2 of plane k.
 template <int SC, int SV, int TX, int TY, bool UPD, bool PIMG, int VAR = 0>
 __device__ __forceinline__ void march_ring(SmemRing<Halo<SC, SV>::S, TX, TY>& sm, const double* __restrict__ W,
                                            double* __restrict__ out, double* __restrict__ Rp,
