@@ -131,6 +131,29 @@ def test_fused_sensor_flags_match_oracle():
         assert np.array_equal(sep[d], ref[d]), d
 
 
+@pytest.mark.parametrize("central,visc,weno", [(6, 4, 5), (4, 4, 3), (8, 8, 5), (2, 6, 1)],
+                         ids=["C6V4W5", "C4V4W3", "C8V8W5", "C2V6W1"])
+def test_hybrid_rk3_orders(central, visc, weno):
+    """RK3 steps of the hybrid scheme (sensor evaluated inside the fused
+    kernel) at other convective, viscous and WENO orders: three steps
+    against the oracle."""
+    case = inputs.Case(**{**SBL.__dict__, "central_order": central, "visc_order": visc, "weno_order": weno})
+    Wn = np.ascontiguousarray(inputs.fields(case))
+    o = oracle_for(case)
+    dt = o.compute_dt(Wn.copy(), case.cfl)
+    h = sx.Handle(case)
+    h.sx_bind(h.to_layout(Wn))
+    for _ in range(3):
+        h.sx_rk3_step(dt)
+    torch.cuda.synchronize()
+    Wo = Wn.copy()
+    Rp = np.zeros((5, case.nz, case.ny, case.nx))
+    for _ in range(3):
+        o.rk3_step(Wo, Rp, dt)
+    err = rel_err_per_field(h.interior(h.state), o.interior(Wo))
+    assert np.all(err < 1e-12), err
+
+
 def test_hybrid_determinism():
     case = SBL
     o = oracle_for(case)
