@@ -98,18 +98,22 @@ template <int S> struct Coef;
 template <> struct Coef<1> {
     static constexpr double a[2] = {0.0, 0.5};
     static constexpr double b[2] = {0.0, 1.0};
+    static constexpr double bsum = b[1];   // sum of the b_l
 };
 template <> struct Coef<2> {
     static constexpr double a[3] = {0.0, 2.0 / 3.0, -1.0 / 12.0};
     static constexpr double b[3] = {0.0, 4.0 / 3.0, -1.0 / 12.0};
+    static constexpr double bsum = b[1] + b[2];   // sum of the b_l
 };
 template <> struct Coef<3> {
     static constexpr double a[4] = {0.0, 3.0 / 4.0, -3.0 / 20.0, 1.0 / 60.0};
     static constexpr double b[4] = {0.0, 3.0 / 2.0, -3.0 / 20.0, 1.0 / 90.0};
+    static constexpr double bsum = b[1] + b[2] + b[3];   // sum of the b_l
 };
 template <> struct Coef<4> {
     static constexpr double a[5] = {0.0, 4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280.0};
     static constexpr double b[5] = {0.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+    static constexpr double bsum = b[1] + b[2] + b[3] + b[4];   // sum of the b_l
 };
 
 // RK3 (Wray) coefficients of one substep, premultiplied by dt.

@@ -108,6 +108,15 @@ __device__ __forceinline__ R visc_pow(R T, const KGas& gas);
 // series in z, |z| < 0.172, 12 terms), and exp r for |r| <= ln2/2 (Taylor,
 // 14 terms), with the exponents split off by frexp / ldexp and ln 2 carried
 // in two parts.
+// A constant handed to the arithmetic as a scalar-register operand at its
+// point of use (FP64 constants other than a few inline values need a
+// register; held in vector registers across a loop they cost 2 registers
+// each and a copy per use).
+__device__ __forceinline__ double kconst(double c)
+{
+    asm volatile("" : "+s"(c));
+    return c;
+}
 __device__ __forceinline__ double visc_pow_f64(double T, double s)
 {
     int e;
@@ -119,17 +128,17 @@ __device__ __forceinline__ double visc_pow_f64(double T, double s)
     const double z = (m - 1.0) * rcp(m + 1.0);
     const double z2 = z * z;
     // atanh(z)/z = sum z^(2k) / (2k+1)
-    double q = 1.0 / 23.0;
-    q = __builtin_fma(q, z2, 1.0 / 21.0);
-    q = __builtin_fma(q, z2, 1.0 / 19.0);
-    q = __builtin_fma(q, z2, 1.0 / 17.0);
-    q = __builtin_fma(q, z2, 1.0 / 15.0);
-    q = __builtin_fma(q, z2, 1.0 / 13.0);
-    q = __builtin_fma(q, z2, 1.0 / 11.0);
-    q = __builtin_fma(q, z2, 1.0 / 9.0);
-    q = __builtin_fma(q, z2, 1.0 / 7.0);
-    q = __builtin_fma(q, z2, 1.0 / 5.0);
-    q = __builtin_fma(q, z2, 1.0 / 3.0);
+    double q = kconst(1.0 / 23.0);
+    q = __builtin_fma(q, z2, kconst(1.0 / 21.0));
+    q = __builtin_fma(q, z2, kconst(1.0 / 19.0));
+    q = __builtin_fma(q, z2, kconst(1.0 / 17.0));
+    q = __builtin_fma(q, z2, kconst(1.0 / 15.0));
+    q = __builtin_fma(q, z2, kconst(1.0 / 13.0));
+    q = __builtin_fma(q, z2, kconst(1.0 / 11.0));
+    q = __builtin_fma(q, z2, kconst(1.0 / 9.0));
+    q = __builtin_fma(q, z2, kconst(1.0 / 7.0));
+    q = __builtin_fma(q, z2, kconst(1.0 / 5.0));
+    q = __builtin_fma(q, z2, kconst(1.0 / 3.0));
     const double lnm = 2.0 * __builtin_fma(z * z2, q, z);
     constexpr double LN2_HI = 6.93147180369123816490e-01, LN2_LO = 1.90821492927058770002e-10;
     // y = s ln T = s (e ln2 + ln m), ln2 in two parts
@@ -138,18 +147,18 @@ __device__ __forceinline__ double visc_pow_f64(double T, double s)
     // exp(y) = 2^n exp(r), r = y - n ln2
     const double n = rint(y * 1.44269504088896340736);
     const double r = __builtin_fma(-n, LN2_LO, __builtin_fma(-n, LN2_HI, y));
-    double p = 1.0 / 87178291200.0;                // 1/14!
-    p = __builtin_fma(p, r, 1.0 / 6227020800.0);
-    p = __builtin_fma(p, r, 1.0 / 479001600.0);
-    p = __builtin_fma(p, r, 1.0 / 39916800.0);
-    p = __builtin_fma(p, r, 1.0 / 3628800.0);
-    p = __builtin_fma(p, r, 1.0 / 362880.0);
-    p = __builtin_fma(p, r, 1.0 / 40320.0);
-    p = __builtin_fma(p, r, 1.0 / 5040.0);
-    p = __builtin_fma(p, r, 1.0 / 720.0);
-    p = __builtin_fma(p, r, 1.0 / 120.0);
-    p = __builtin_fma(p, r, 1.0 / 24.0);
-    p = __builtin_fma(p, r, 1.0 / 6.0);
+    double p = kconst(1.0 / 87178291200.0);                // 1/14!
+    p = __builtin_fma(p, r, kconst(1.0 / 6227020800.0));
+    p = __builtin_fma(p, r, kconst(1.0 / 479001600.0));
+    p = __builtin_fma(p, r, kconst(1.0 / 39916800.0));
+    p = __builtin_fma(p, r, kconst(1.0 / 3628800.0));
+    p = __builtin_fma(p, r, kconst(1.0 / 362880.0));
+    p = __builtin_fma(p, r, kconst(1.0 / 40320.0));
+    p = __builtin_fma(p, r, kconst(1.0 / 5040.0));
+    p = __builtin_fma(p, r, kconst(1.0 / 720.0));
+    p = __builtin_fma(p, r, kconst(1.0 / 120.0));
+    p = __builtin_fma(p, r, kconst(1.0 / 24.0));
+    p = __builtin_fma(p, r, kconst(1.0 / 6.0));
     p = __builtin_fma(p, r, 0.5);
     p = __builtin_fma(p, r, 1.0);
     p = __builtin_fma(p, r, 1.0);
@@ -276,15 +285,19 @@ __device__ __forceinline__ Node<R> ring_read(const R* z, R igM2)
     }
 }
 
-// One direction of the output node, streaming the stencil pairs l = 1..S
-// so only the centre and the two nodes at distance l are live. Adds the
-// convective derivative in the pair-difference form of the split flux,
+// One direction of the output node over the stencil pairs l = 1..S (FP64
+// reads every node first; FP32 streams the pairs so only the centre and the
+// two nodes at distance l are live). Adds the convective derivative in the
+// pair-difference form of the split flux,
 //   F_{i+1/2} - F_{i-1/2} = sum_l 2 a_l [P_l(i) - P_l(i-l)],
 //   P_l(n) = 1/8 (rho_n + rho_{n+l})(ud_n + ud_{n+l})(phi_n + phi_{n+l}),
-// phi in {1, u, v, w, H}, pressure 1/2 (p_n + p_{n+l}) in the D-momentum,
-// to acc and returns first derivatives gd = (u, v, w, T)_n and the pure
-// second derivatives dd = (u, v, w, T)_nn (sc: metric 1/h or eta_y;
-// sc2 = sc^2; scy = eta_yy along y, 0 otherwise).
+// phi in {1, u, v, w, H}, pressure 1/2 (p_n + p_{n+l}) in the D-momentum
+// (FP64: differences of rho T, scaled once by 1/(gamma M^2)), to acc and
+// returns first derivatives gd = (u, v, w, T)_n and the pure second
+// derivatives dd = (u, v, w, T)_nn, the latter as
+// sum_l b_l (f_{n+l} + f_{n-l}) - 2 (sum_l b_l) f_n (sc: metric 1/h or
+// eta_y; sc2 = sc^2; scy = eta_yy along y, 0 otherwise; kgas: the gas,
+// needed by the convective FP64 and KEEP-n forms).
 // KEEP-n two-point flux (FP64). The entropy-conserving, kinetic-energy
 // preserving pair flux of nodes A, B along direction D:
 //   F_rho = rho_ln (ud_A + ud_B)/2,  F_mom = F_rho (u_A + u_B)/2 + (p_A + p_B)/2 e_D,
@@ -331,7 +344,7 @@ __device__ __forceinline__ void keep_pair(const Node<double>& A, const Node<doub
 template <int SC, int SV, int D, bool CONV, bool VISC, bool KEEP = false, bool D1 = false, typename R,
           typename Get>
 __device__ __forceinline__ void stencil_dir(Get get, R sc, R sc2, R scy, R (&acc)[NV], R (&gd)[4],
-                                            R (&dd)[4], const KGas* kgas = nullptr)
+                                            R (&dd)[4], const KGas* kgas)
 {
     // D1 (convective only): gd[0..2] return the differences u, v, w of the
     // two nodes at distance 1, for the second-order sensor
@@ -340,9 +353,21 @@ __device__ __forceinline__ void stencil_dir(Get get, R sc, R sc2, R scy, R (&acc
     const Node<R> C = get(0);
     R f0 = 0, f1 = 0, f2 = 0, f3 = 0, f4 = 0, fp = 0;
     R s1[4] = {0, 0, 0, 0}, s2[4] = {0, 0, 0, 0};
+    // FP64: every stencil node is read before the arithmetic starts, so the
+    // LDS reads of a direction are in flight together (the FP32 form streams
+    // the pairs, for its register budget)
+    constexpr bool PRE = std::is_same<R, double>::value;
+    Node<R> Ms[SL], Ps[SL];
+    if constexpr (PRE) {
+#pragma unroll
+        for (int l = 1; l <= SL; ++l) {
+            Ms[l - 1] = get(-l);
+            Ps[l - 1] = get(l);
+        }
+    }
 #pragma unroll
     for (int l = 1; l <= SL; ++l) {
-        const Node<R> M = get(-l), P = get(l);
+        const Node<R> M = PRE ? Ms[l - 1] : get(-l), P = PRE ? Ps[l - 1] : get(l);
         if constexpr (D1 && !VISC) {
             if (l == 1) {
                 gd[0] = P.u - M.u;
@@ -377,7 +402,12 @@ __device__ __forceinline__ void stencil_dir(Get get, R sc, R sc2, R scy, R (&acc
             f2 = fmar(mp, P.v, fmar(-mm, M.v, f2));
             f3 = fmar(mp, P.w, fmar(-mm, M.w, f3));
             f4 = fmar(mp, P.H, fmar(-mm, M.H, f4));
-            fp += (R(4) * cl) * (P.p - M.p);
+            if constexpr (std::is_same<R, double>::value) {
+                // p = rho T / (gamma M^2): the pair differences of rho T, scaled once below
+                fp = fmar(R(4) * cl, fmar(P.r, P.T, -(M.r * M.T)), fp);
+            } else {
+                fp += (R(4) * cl) * (P.p - M.p);
+            }
         }
         if (VISC && l <= SV) {
             const R al = R(Coef<SV>::a[l]), bl = R(Coef<SV>::b[l]);
@@ -385,10 +415,10 @@ __device__ __forceinline__ void stencil_dir(Get get, R sc, R sc2, R scy, R (&acc
             s1[1] += al * (P.v - M.v);
             s1[2] += al * (P.w - M.w);
             s1[3] += al * (P.T - M.T);
-            s2[0] += bl * ((P.u - R(2) * C.u) + M.u);
-            s2[1] += bl * ((P.v - R(2) * C.v) + M.v);
-            s2[2] += bl * ((P.w - R(2) * C.w) + M.w);
-            s2[3] += bl * ((P.T - R(2) * C.T) + M.T);
+            s2[0] += bl * (P.u + M.u);
+            s2[1] += bl * (P.v + M.v);
+            s2[2] += bl * (P.w + M.w);
+            s2[3] += bl * (P.T + M.T);
         }
     }
     if (CONV) {
@@ -398,6 +428,7 @@ __device__ __forceinline__ void stencil_dir(Get get, R sc, R sc2, R scy, R (&acc
             f3 = fmar(C.w, f0, f3);
             f4 = fmar(C.H, f0, f4);
             f0 *= R(2);
+            if constexpr (std::is_same<R, double>::value) fp *= R(kgas->igM2);
             if (D == 0) f1 += fp;
             if (D == 1) f2 += fp;
             if (D == 2) f3 += fp;
@@ -409,6 +440,11 @@ __device__ __forceinline__ void stencil_dir(Get get, R sc, R sc2, R scy, R (&acc
         acc[4] -= sc * f4;
     }
     if (VISC) {
+        constexpr double B2 = 2.0 * Coef<SV>::bsum;
+        s2[0] = fmar(R(-B2), C.u, s2[0]);
+        s2[1] = fmar(R(-B2), C.v, s2[1]);
+        s2[2] = fmar(R(-B2), C.w, s2[2]);
+        s2[3] = fmar(R(-B2), C.T, s2[3]);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             gd[q] = sc * s1[q];
@@ -785,24 +821,24 @@ __device__ __forceinline__ void march(Smem<Halo<SC, SV>::S, TX, TY, R>& sm, cons
                 return znode(sl);
             };
             if (mask & SX_CONV_X) {
-                if (visc) stencil_dir<SC, SV, 0, true, true>(getx, dxi, dxi * dxi, R(0), acc, gx, dd);
-                else stencil_dir<SC, SV, 0, true, false>(getx, dxi, dxi * dxi, R(0), acc, gx, dd);
+                if (visc) stencil_dir<SC, SV, 0, true, true>(getx, dxi, dxi * dxi, R(0), acc, gx, dd, &gas);
+                else stencil_dir<SC, SV, 0, true, false>(getx, dxi, dxi * dxi, R(0), acc, gx, dd, &gas);
             } else if (visc) {
-                stencil_dir<SC, SV, 0, false, true>(getx, dxi, dxi * dxi, R(0), acc, gx, dd);
+                stencil_dir<SC, SV, 0, false, true>(getx, dxi, dxi * dxi, R(0), acc, gx, dd, nullptr);
             }
             if (visc) visc_linear<0>(dd, mu, kcd, uc, vc, wc_, acc);
             if (mask & SX_CONV_Y) {
-                if (visc) stencil_dir<SC, SV, 1, true, true>(gety, ey, ey * ey, eyy, acc, gy, dd);
-                else stencil_dir<SC, SV, 1, true, false>(gety, ey, ey * ey, eyy, acc, gy, dd);
+                if (visc) stencil_dir<SC, SV, 1, true, true>(gety, ey, ey * ey, eyy, acc, gy, dd, &gas);
+                else stencil_dir<SC, SV, 1, true, false>(gety, ey, ey * ey, eyy, acc, gy, dd, &gas);
             } else if (visc) {
-                stencil_dir<SC, SV, 1, false, true>(gety, ey, ey * ey, eyy, acc, gy, dd);
+                stencil_dir<SC, SV, 1, false, true>(gety, ey, ey * ey, eyy, acc, gy, dd, nullptr);
             }
             if (visc) visc_linear<1>(dd, mu, kcd, uc, vc, wc_, acc);
             if (mask & SX_CONV_Z) {
-                if (visc) stencil_dir<SC, SV, 2, true, true>(getz, dzi, dzi * dzi, R(0), acc, gz, dd);
-                else stencil_dir<SC, SV, 2, true, false>(getz, dzi, dzi * dzi, R(0), acc, gz, dd);
+                if (visc) stencil_dir<SC, SV, 2, true, true>(getz, dzi, dzi * dzi, R(0), acc, gz, dd, &gas);
+                else stencil_dir<SC, SV, 2, true, false>(getz, dzi, dzi * dzi, R(0), acc, gz, dd, &gas);
             } else if (visc) {
-                stencil_dir<SC, SV, 2, false, true>(getz, dzi, dzi * dzi, R(0), acc, gz, dd);
+                stencil_dir<SC, SV, 2, false, true>(getz, dzi, dzi * dzi, R(0), acc, gz, dd, nullptr);
             }
             // enthalpy shift correction of the convective energy flux (FP64)
             const double accE_shift = href * double(acc[0]);
@@ -1257,11 +1293,11 @@ __device__ __forceinline__ void march_split(SmemSplit<Halo<SC, SV>::S, TX, TY, R
                     sl = sl < 0 ? sl + Q : (sl >= Q ? sl - Q : sl);
                     return znode(sl);
                 };
-                stencil_dir<SC, SV, 0, false, true>(getx, dxi, dxi * dxi, R(0), acc, gx, dd);
+                stencil_dir<SC, SV, 0, false, true>(getx, dxi, dxi * dxi, R(0), acc, gx, dd, nullptr);
                 visc_linear<0>(dd, mu, kcd, uc, vc, wc_, acc);
-                stencil_dir<SC, SV, 1, false, true>(gety, ey, ey * ey, eyy, acc, gy, dd);
+                stencil_dir<SC, SV, 1, false, true>(gety, ey, ey * ey, eyy, acc, gy, dd, nullptr);
                 visc_linear<1>(dd, mu, kcd, uc, vc, wc_, acc);
-                stencil_dir<SC, SV, 2, false, true>(getz, dzi, dzi * dzi, R(0), acc, gz, dd);
+                stencil_dir<SC, SV, 2, false, true>(getz, dzi, dzi * dzi, R(0), acc, gz, dd, nullptr);
                 visc_linear<2>(dd, mu, kcd, uc, vc, wc_, acc);
                 // mixed z parts of mu/3 d_i(div u): d_z d_x w, d_z d_y w,
                 // d_z (d_x u + d_y v) (the x-y parts are the convective role's)
@@ -1470,13 +1506,18 @@ __device__ __forceinline__ void march_ring(SmemRing<Halo<SC, SV>::S, TX, TY>& sm
         R xw[QV], yw[QV], xu[QV], yv[QV];
 #pragma unroll
         for (int t = 0; t < QV; ++t) {
-            const dbl2* rx = reinterpret_cast<const dbl2*>(hp + 6 * (c + t - SV));
-            const dbl2* ry = reinterpret_cast<const dbl2*>(hp + 6 * (c + (t - SV) * HX));
-            const dbl2 ax = rx[0], bx = rx[1], ay = ry[0], by = ry[1];
-            xu[t] = ax.x;
-            xw[t] = bx.x;
-            yv[t] = ay.y;
-            yw[t] = by.x;
+            // the two values needed from each record as one 64-bit pair
+            // read ((u, w) along x, (v, w) along y). Half-used 128-bit reads
+            // recycle their dead halves as the next read's destination,
+            // which serialises the reads; the pair reads cost 2-way bank
+            // conflicts at the 48-byte record stride but run faster than
+            // whole 128-bit records held live until all are issued
+            const double* rx = hp + 6 * (c + t - SV);
+            const double* ry = hp + 6 * (c + (t - SV) * HX);
+            xu[t] = rx[0];
+            xw[t] = rx[2];
+            yv[t] = ry[1];
+            yw[t] = ry[2];
         }
         m0[Q - 1] = dxi * d1<SV>(xw);
         m1[Q - 1] = ey * d1<SV>(yw);
@@ -1628,10 +1669,10 @@ __device__ __forceinline__ void march_ring(SmemRing<Halo<SC, SV>::S, TX, TY>& sm
                 // per node for the face flags
                 if (active) {
                     R dx[4], dy[4], dz[4], dd[4];
-                    stencil_dir<SC, SV, 0, true, false, false, true>(gx_, dxi, dxi, R(0), acc, dx, dd);
-                    stencil_dir<SC, SV, 1, true, false, false, true>(gy_, ey, ey, R(0), acc, dy, dd);
+                    stencil_dir<SC, SV, 0, true, false, false, true>(gx_, dxi, dxi, R(0), acc, dx, dd, &gas);
+                    stencil_dir<SC, SV, 1, true, false, false, true>(gy_, ey, ey, R(0), acc, dy, dd, &gas);
                     auto gz_ = [&](int t) { return znode_at(k, t); };
-                    stencil_dir<SC, SV, 2, true, false, false, true>(gz_, dzi, dzi, R(0), acc, dz, dd);
+                    stencil_dir<SC, SV, 2, true, false, false, true>(gz_, dzi, dzi, R(0), acc, dz, dd, &gas);
                     const double ix = 0.5 * g.dxi, iy = 0.5 * g.eta_y[j], iz = 0.5 * g.dzi;
                     const double ux = dx[0] * ix, vx = dx[1] * ix, wx = dx[2] * ix;
                     const double uy = dy[0] * iy, vy = dy[1] * iy, wy = dy[2] * iy;
@@ -1692,7 +1733,7 @@ __device__ __forceinline__ void march_ring(SmemRing<Halo<SC, SV>::S, TX, TY>& sm
             auto gy_ = [&](int t) { return gety(k, t); };
             auto gz_ = [&](int t) { return znode_at(k, t); };
             if (active && visc) {
-                stencil_dir<SC, SV, 0, false, true>(gx_, dxi, dxi * dxi, R(0), acc, gx, dd);
+                stencil_dir<SC, SV, 0, false, true>(gx_, dxi, dxi * dxi, R(0), acc, gx, dd, nullptr);
                 visc_linear<0>(dd, mu, kcd, uc, vc, wc_, acc);
             }
             // the loads of plane k+S+1 go out here, after the x stencil,
@@ -1703,11 +1744,11 @@ __device__ __forceinline__ void march_ring(SmemRing<Halo<SC, SV>::S, TX, TY>& sm
             if (k + 1 < k1) fetch(fb, k + 1 + S);
             sched_fence();
             if (active && visc) {
-                stencil_dir<SC, SV, 1, false, true>(gy_, ey, ey * ey, eyy, acc, gy, dd);
+                stencil_dir<SC, SV, 1, false, true>(gy_, ey, ey * ey, eyy, acc, gy, dd, nullptr);
                 visc_linear<1>(dd, mu, kcd, uc, vc, wc_, acc);
             }
             if (active && visc) {
-                stencil_dir<SC, SV, 2, false, true>(gz_, dzi, dzi * dzi, R(0), acc, gz, dd);
+                stencil_dir<SC, SV, 2, false, true>(gz_, dzi, dzi * dzi, R(0), acc, gz, dd, nullptr);
                 visc_linear<2>(dd, mu, kcd, uc, vc, wc_, acc);
             }
             if (active && visc) {
