@@ -294,7 +294,7 @@ __device__ __forceinline__ Node<R> ring_read(const R* z, R igM2)
 // phi in {1, u, v, w, H}, pressure 1/2 (p_n + p_{n+l}) in the D-momentum
 // (FP64: differences of rho T, scaled once by 1/(gamma M^2)), to acc and
 // returns first derivatives gd = (u, v, w, T)_n and the pure second
-// derivatives dd = (u, v, w, T)_nn, the latter as
+// derivatives dd = (u, v, w, T)_nn, the latter in FP64 as
 // sum_l b_l (f_{n+l} + f_{n-l}) - 2 (sum_l b_l) f_n (sc: metric 1/h or
 // eta_y; sc2 = sc^2; scy = eta_yy along y, 0 otherwise; kgas: the gas,
 // needed by the convective FP64 and KEEP-n forms).
@@ -415,10 +415,17 @@ __device__ __forceinline__ void stencil_dir(Get get, R sc, R sc2, R scy, R (&acc
             s1[1] += al * (P.v - M.v);
             s1[2] += al * (P.w - M.w);
             s1[3] += al * (P.T - M.T);
-            s2[0] += bl * (P.u + M.u);
-            s2[1] += bl * (P.v + M.v);
-            s2[2] += bl * (P.w + M.w);
-            s2[3] += bl * (P.T + M.T);
+            if constexpr (std::is_same<R, double>::value) {
+                s2[0] += bl * (P.u + M.u);
+                s2[1] += bl * (P.v + M.v);
+                s2[2] += bl * (P.w + M.w);
+                s2[3] += bl * (P.T + M.T);
+            } else {   // FP32 keeps the per-pair second differences (smaller rounding)
+                s2[0] += bl * ((P.u - R(2) * C.u) + M.u);
+                s2[1] += bl * ((P.v - R(2) * C.v) + M.v);
+                s2[2] += bl * ((P.w - R(2) * C.w) + M.w);
+                s2[3] += bl * ((P.T - R(2) * C.T) + M.T);
+            }
         }
     }
     if (CONV) {
@@ -440,15 +447,18 @@ __device__ __forceinline__ void stencil_dir(Get get, R sc, R sc2, R scy, R (&acc
         acc[4] -= sc * f4;
     }
     if (VISC) {
-        constexpr double B2 = 2.0 * Coef<SV>::bsum;
-        s2[0] = fmar(R(-B2), C.u, s2[0]);
-        s2[1] = fmar(R(-B2), C.v, s2[1]);
-        s2[2] = fmar(R(-B2), C.w, s2[2]);
-        s2[3] = fmar(R(-B2), C.T, s2[3]);
+        if constexpr (std::is_same<R, double>::value) {
+            constexpr double B2 = 2.0 * Coef<SV>::bsum;
+            s2[0] = fmar(R(-B2), C.u, s2[0]);
+            s2[1] = fmar(R(-B2), C.v, s2[1]);
+            s2[2] = fmar(R(-B2), C.w, s2[2]);
+            s2[3] = fmar(R(-B2), C.T, s2[3]);
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             gd[q] = sc * s1[q];
-            dd[q] = sc2 * s2[q] + scy * s1[q];
+            // the metric term eta_yy D_eta f exists along y only
+            dd[q] = D == 1 ? sc2 * s2[q] + scy * s1[q] : sc2 * s2[q];
         }
     }
 }
