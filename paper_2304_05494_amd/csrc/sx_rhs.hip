@@ -99,15 +99,6 @@ struct Halo {
     static constexpr int S = SC > SV ? SC : SV;
 };
 
-// Viscosity law T^s: FP64 through exp(s log T); FP32 through the hardware
-// base-2 logarithm and exponential.
-template <typename R>
-__device__ __forceinline__ R visc_pow(R T, const KGas& gas);
-// FP64 T^s = exp(s ln T) for T > 0 from two short series (relative error a
-// few ulp): ln m = 2 atanh z, z = (m-1)/(m+1), m in [1/sqrt2, sqrt2) (odd
-// series in z, |z| < 0.172, 12 terms), and exp r for |r| <= ln2/2 (Taylor,
-// 14 terms), with the exponents split off by frexp / ldexp and ln 2 carried
-// in two parts.
 // A constant handed to the arithmetic as a scalar-register operand at its
 // point of use (FP64 constants other than a few inline values need a
 // register; held in vector registers across a loop they cost 2 registers
@@ -117,6 +108,16 @@ __device__ __forceinline__ double kconst(double c)
     asm volatile("" : "+s"(c));
     return c;
 }
+
+// Viscosity law T^s: FP64 through exp(s log T); FP32 through the hardware
+// base-2 logarithm and exponential.
+template <typename R>
+__device__ __forceinline__ R visc_pow(R T, const KGas& gas);
+// FP64 T^s = exp(s ln T) for T > 0 from two short series (relative error a
+// few ulp): ln m = 2 atanh z, z = (m-1)/(m+1), m in [1/sqrt2, sqrt2) (odd
+// series in z, |z| < 0.172, 12 terms), and exp r for |r| <= ln2/2 (Taylor,
+// 14 terms), with the exponents split off by frexp / ldexp and ln 2 carried
+// in two parts.
 __device__ __forceinline__ double visc_pow_f64(double T, double s)
 {
     int e;
