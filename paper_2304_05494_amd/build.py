@@ -27,6 +27,11 @@ FLAGS = [
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]
 
+# The fused RHS/update kernels are latency-bound at two waves per SIMD: the
+# instruction-level-parallelism scheduling strategy of the AMDGPU backend
+# measured 1 % faster on them than the default occupancy-driven one.
+SOURCE_FLAGS = {"sx_rhs.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
+
 
 def build(verbose: bool = False, extra: list[str] | None = None, jobs: int | None = None) -> str:
     from concurrent.futures import ThreadPoolExecutor
@@ -36,7 +41,7 @@ def build(verbose: bool = False, extra: list[str] | None = None, jobs: int | Non
 
     def compile_one(src: str) -> str:
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
-        cmd = [HIPCC, *FLAGS, *(extra or []), "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC, *FLAGS, *SOURCE_FLAGS.get(src, []), *(extra or []), "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
